@@ -1,0 +1,218 @@
+/*
+ * amr.h -- C ABI of the MI355X octree AMR ray caster.
+ *
+ * The library casts one ray per pixel through an octree AMR volume truncated
+ * at a camera-defined maximum level and accumulates, per ray, one of three
+ * projections (Labadens et al., "Volume Rendering of AMR Simulations"):
+ *   AMR_SUM    sum over the cells met of value x chord length (Sec. 2.2);
+ *   AMR_MAX    maximum of the values met, a maximum-intensity projection
+ *              (named in Sec. 2.1);
+ *   AMR_WMEAN  weighted mean of a field along the ray, weight x chord as the
+ *              measure (a mass-weighted mean when the weight is the density;
+ *              the per-cell fields are those listed in Sec. 1).
+ * Truncation follows Sec. 2: every cell at the maximum level is treated as a
+ * leaf and carries the restricted value of its subtree.
+ *
+ * Conventions for every entry point:
+ *  - Return an amr_status; nothing throws across the ABI.  On error,
+ *    amr_last_error() (thread-local) describes it and no output is written.
+ *  - "device" pointers are HIP device memory of the current device; "host"
+ *    pointers are ordinary process memory.  The caller owns every buffer it
+ *    passes in; the library owns trees, batches and LOD models, which are
+ *    released with the matching *_free call.
+ *  - Stream-ordered calls take a hipStream_t passed as amr_stream (NULL =
+ *    the null stream).  They enqueue work and return; outputs are valid
+ *    after the stream is synchronised.  They allocate nothing.
+ *  - Positions are integers in units of 2^-28 of the unit box [0,1)^3; the
+ *    root cell is level 0; a level-l cell has side 2^-l.  Cells are
+ *    half-open boxes [a, b).
+ */
+#ifndef AMR_H_
+#define AMR_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  AMR_OK = 0,
+  AMR_EINVAL = 1,     /* bad argument (null, range, alignment, NaN/Inf) */
+  AMR_ETREE = 2,      /* leaves do not tile the box as a complete octree */
+  AMR_ENOMEM = 3,     /* host or device allocation failed */
+  AMR_EHIP = 4,       /* a HIP runtime call or kernel launch failed */
+  AMR_ECAPACITY = 5,  /* an output buffer is too small */
+  AMR_ESTALE = 6,     /* a batch refers to a tree that was freed */
+  AMR_EMODEL = 7      /* LOD model shape or version mismatch */
+} amr_status;
+
+typedef enum { AMR_SUM = 0, AMR_MAX = 1, AMR_WMEAN = 2 } amr_op;
+typedef enum { AMR_HOST = 0, AMR_DEVICE = 1 } amr_location;
+
+typedef void* amr_stream; /* hipStream_t */
+typedef struct amr_tree amr_tree;
+
+/* Thread-local description of the last error (never NULL). */
+const char* amr_last_error(void);
+
+/* ------------------------------------------------------------------ tree */
+
+/* Leaves of an octree: n leaves, leaf q at level level[q] (0..24) with
+ * integer coordinates 0 <= ix,iy,iz < 2^level.  fields[f * field_stride + q]
+ * is fp32 field f of leaf q (field 0 is conventionally the density, fields
+ * 1..3 the velocity).  location says where the five arrays live. */
+typedef struct {
+  int64_t n;
+  const int32_t* level;
+  const int32_t* ix;
+  const int32_t* iy;
+  const int32_t* iz;
+  const float* fields;
+  int32_t nfields;       /* 1..8 */
+  int32_t location;      /* amr_location */
+  int64_t field_stride;  /* >= n */
+} amr_leaves;
+
+/* How interior (truncated) cells get their values (Sec. 2 leaves this open;
+ * the reading taken is RAMSES-style conservative restriction):
+ * restrict_weight[f] = -1: field f is the volume mean of the 8 children;
+ * restrict_weight[f] = w >= 0: field f is the mean weighted by field w
+ * (mass-weighted for w = density); field w must itself be a volume mean.
+ * Means are taken in fp64, children summed in Morton child order 0..7
+ * (bit0 = x, bit1 = y, bit2 = z), and rounded once to fp32.
+ * use_defaults != 0 ignores restrict_weight: field 0 volume mean, every
+ * other field weighted by field 0.  host_only != 0 keeps the tree in host
+ * memory (inspection and CPU tests; such a tree cannot be rendered). */
+typedef struct {
+  int32_t restrict_weight[8];
+  int32_t use_defaults;
+  int32_t host_only;
+} amr_build_opts;
+
+/* Build the linear octree (synchronous).  Validates that the leaves tile the
+ * unit box as a complete octree (AMR_ETREE on a gap, an overlap, a
+ * duplicate or a coordinate out of range; AMR_EINVAL on a NaN/Inf field or a
+ * level outside 0..24), sorts them in Morton order, lays every cell out
+ * level by level in Morton order (the 8 children of a cell contiguous), and
+ * uploads per-cell arrays: first-child index (int32, -1 for leaves), fp32
+ * values [nfields][ncells] and the deepest leaf level below each cell
+ * (uint8).  The caller's arrays are not retained.  *out receives a
+ * library-owned tree, released by amr_tree_free. */
+amr_status amr_build_linear_octree(const amr_leaves* in, const amr_build_opts* opt, amr_stream s, amr_tree** out);
+void amr_tree_free(amr_tree* t);
+
+typedef struct {
+  int64_t ncells;
+  int64_t nleaves;
+  int32_t nfields;
+  int32_t lmax;        /* deepest leaf level */
+  int32_t levelmin;    /* shallowest leaf level: levels 0..levelmin are complete */
+  int32_t host_only;
+  int64_t cells_per_level[25];
+  int64_t level_offset[26];
+  int64_t device_bytes;
+} amr_tree_info_t;
+
+amr_status amr_tree_info(const amr_tree* t, amr_tree_info_t* info);
+
+/* Per-cell arrays of the tree, in the library's layout (see
+ * amr_build_linear_octree): host pointers for a host_only tree, device
+ * pointers otherwise.  They stay valid until amr_tree_free. */
+amr_status amr_tree_arrays(const amr_tree* t, const int32_t** child, const float** values,
+                           const uint8_t** maxdepth);
+
+/* ---------------------------------------------------------------- camera */
+
+/* Camera description (box units).  kind 0 = perspective (fov_y, radians),
+ * 1 = orthographic (ortho_height).  W x H pixels.  max_level >= 0 fixes the
+ * deepest level read; -1 derives it from the pixel footprint (Sec. 2: cells
+ * much smaller than a pixel are discarded). */
+typedef struct {
+  int32_t kind;
+  int32_t W, H;
+  int32_t max_level;
+  int32_t level_bias;
+  int32_t pad_;
+  double eye[3], target[3], up[3];
+  double fov_y;
+  double ortho_height;
+} amr_camera_desc;
+
+/* Quantised camera: the exact integer ray contract.  For pixel (i, j)
+ * (i = column, j = row, j = 0 at the bottom), with a = 2i + 1 - W and
+ * b = 2j + 1 - H (rays through pixel centres, Sec. 2.2 "one ray per pixel"):
+ *   perspective:  origin O,              direction F + a U + b V
+ *   orthographic: origin O + a U + b V,  direction F
+ * Origins lie in [-2^30, 2^30) and direction components in (-2^30, 2^30). */
+typedef struct {
+  int32_t kind, W, H, max_level;
+  int64_t O[3], F[3], U[3], V[3];
+} amr_camera;
+
+/* Quantise a camera (host only, no GPU needed).  With f = target - eye,
+ * fh = f / |f|, rh = (up x fh) / |up x fh|, uh = fh x rh, s = tan(fov_y/2)/H
+ * (perspective) or ortho_height / (2H) (orthographic):
+ *   O = rne(eye 2^28), F = rne(fh 2^28), U = rne(rh s 2^28), V = rne(uh s 2^28)
+ * in fp64, each norm as sqrt((x^2 + y^2) + z^2), no fused operations.
+ * Automatic max_level (Sec. 2): the smallest L >= 0 with 2^-L <= p, p the
+ * pixel footprint (ortho_height / H, or 2 |f| tan(fov_y/2) / H at the
+ * target), plus level_bias, clamped to [0, 24] and to the tree's deepest
+ * level when t is not NULL.  AMR_EINVAL on a degenerate basis, W or H
+ * outside 1..32768, origins or directions outside the ranges above, or an
+ * explicit max_level outside 0..24. */
+amr_status amr_set_camera(const amr_camera_desc* d, const amr_tree* t, amr_camera* out);
+
+/* ---------------------------------------------------------------- render */
+
+typedef struct {
+  int32_t field;         /* value field for SUM / MAX; for WMEAN the scalar
+                            field, or the first of 3 velocity components */
+  int32_t weight_field;  /* WMEAN weight (density) */
+  int32_t los_velocity;  /* WMEAN: f = (v_field, v_field+1, v_field+2) . d/|d| */
+  int32_t variant;       /* kernel variant; -1 = default (see amr_variant_count) */
+} amr_render_opts;
+
+/* Render one image (Sec. 2.2: one ray per pixel, top-down descent to the
+ * leaves of the truncated tree, value x chord summed in any order).
+ * out: device fp32, H x W row-major (out[j*W + i]).
+ *   SUM   sum of v * chord (box units); 0 for rays that miss the box.
+ *   MAX   maximum of v; -inf for rays that miss the box.
+ *   WMEAN sum(w f chord) / sum(w chord), 0 when the weight integral is 0.
+ * aux: device fp32 H x W or NULL; for WMEAN receives sum(w chord).
+ * Cell decisions are exact integer predicates, so the cell sequence of
+ * every ray is deterministic; sums are fp32 Kahan-compensated; chord
+ * lengths come from an exact integer numerator, in fp64 for cells at level
+ * 18 and deeper.  Every variant gives bit-identical output. */
+amr_status amr_render(const amr_tree* t, const amr_camera* cam, amr_op op, const amr_render_opts* opts, float* out,
+                      float* aux, amr_stream s);
+
+/* Number of kernel variants (ray-packet shape, waves per block, descent
+ * mode) amr_render_opts.variant may select, and a short name for each. */
+int32_t amr_variant_count(void);
+const char* amr_variant_name(int32_t v);
+
+/* ---------------------------------------------------------------- debug */
+
+/* Segments (cells met) per ray for every pixel: counts (device int32 H x W,
+ * may be NULL) and their total (device int64, 1 element, overwritten). */
+amr_status amr_count_segments(const amr_tree* t, const amr_camera* cam, int32_t* counts, int64_t* total,
+                              amr_stream s);
+
+/* Cell sequences of the rays ray_ids[0..n) (pixel index j*W + i, device
+ * int64).  offsets (device int64, n + 1) must already hold the exclusive
+ * prefix sum of the rays' segment counts (from amr_count_segments);
+ * cells (device int32, 4 per segment: level, ix, iy, iz, unmirrored) receive
+ * the cells in the order the ray meets them.  AMR_ECAPACITY is not
+ * detectable on the device: the caller sizes cells from offsets[n]. */
+amr_status amr_trace_rays(const amr_tree* t, const amr_camera* cam, const int64_t* ray_ids, int64_t n,
+                          const int64_t* offsets, int32_t* cells, amr_stream s);
+
+/* Segment counts of the rays ray_ids[0..n) only (device int32 counts[n]). */
+amr_status amr_count_rays(const amr_tree* t, const amr_camera* cam, const int64_t* ray_ids, int64_t n,
+                          int32_t* counts, amr_stream s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AMR_H_ */

@@ -1,0 +1,194 @@
+"""MI355X octree AMR ray caster -- thin Python binding over libamr.so.
+
+Every step of the path runs in the library's HIP kernels; this module only
+marshals arguments through ctypes.  PyTorch supplies device memory and the
+stream (``torch.cuda.current_stream().cuda_stream``).  The library must be
+built (``python -m paper_1210_8014_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+from . import _abi
+from ._abi import (AMR_DEVICE, AMR_HOST, AMR_MAX, AMR_SUM, AMR_WMEAN, BuildOpts, Camera, CameraDesc, LeavesC,
+                   RenderOpts, TreeInfo)
+
+SUM, MAX, WMEAN = AMR_SUM, AMR_MAX, AMR_WMEAN
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libamr.so")
+
+
+class AmrError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_abi.STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libamr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1210_8014_amd.build`")
+        _lib = _abi.declare(ctypes.CDLL(LIB_PATH))
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise AmrError(rc, lib().amr_last_error().decode())
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    """Address of a torch tensor or numpy array (None -> NULL)."""
+    if t is None:
+        return ctypes.c_void_p(0)
+    if isinstance(t, np.ndarray):
+        return ctypes.c_void_p(t.ctypes.data)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------------ tree
+
+class Tree:
+    """Library-owned linear octree (amr_build_linear_octree)."""
+
+    def __init__(self, leaves, restrict=None, host_only: bool = False, stream=None):
+        L = lib()
+        lv = np.ascontiguousarray(leaves.level, np.int32)
+        ix = np.ascontiguousarray(leaves.ix, np.int32)
+        iy = np.ascontiguousarray(leaves.iy, np.int32)
+        iz = np.ascontiguousarray(leaves.iz, np.int32)
+        fl = np.ascontiguousarray(leaves.fields, np.float32)
+        if fl.ndim == 1:
+            fl = fl.reshape(1, -1)
+        c = LeavesC()
+        c.n = lv.shape[0]
+        c.level, c.ix, c.iy, c.iz = (x.ctypes.data for x in (lv, ix, iy, iz))
+        c.fields = fl.ctypes.data
+        c.nfields = fl.shape[0]
+        c.location = AMR_HOST
+        c.field_stride = fl.shape[1]
+        o = BuildOpts()
+        if restrict is None:
+            o.use_defaults = 1
+        else:
+            for k, w in enumerate(restrict):
+                o.restrict_weight[k] = int(w)
+        o.host_only = int(bool(host_only))
+        h = ctypes.c_void_p()
+        _check(L.amr_build_linear_octree(ctypes.byref(c), ctypes.byref(o),
+                                         ctypes.c_void_p(0) if host_only else _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.info = TreeInfo()
+        _check(L.amr_tree_info(h, ctypes.byref(self.info)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def lmax(self) -> int:
+        return int(self.info.lmax)
+
+    @property
+    def ncells(self) -> int:
+        return int(self.info.ncells)
+
+    def arrays(self):
+        """(child, values, maxdepth) addresses: host for host_only trees."""
+        c, v, m = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        _check(lib().amr_tree_arrays(self._h, ctypes.byref(c), ctypes.byref(v), ctypes.byref(m)))
+        return c.value, v.value, m.value
+
+    def host_arrays(self):
+        """numpy copies of the per-cell arrays of a host_only tree."""
+        assert self.info.host_only
+        c, v, m = self.arrays()
+        n, nf = self.ncells, int(self.info.nfields)
+        child = np.ctypeslib.as_array(ctypes.cast(c, ctypes.POINTER(ctypes.c_int32)), (n,)).copy()
+        vals = np.ctypeslib.as_array(ctypes.cast(v, ctypes.POINTER(ctypes.c_float)), (nf * n,)).copy().reshape(nf, n)
+        md = np.ctypeslib.as_array(ctypes.cast(m, ctypes.POINTER(ctypes.c_uint8)), (n,)).copy()
+        return child, vals, md
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().amr_tree_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- camera
+
+_KIND = {"persp": 0, "ortho": 1}
+
+
+def camera_desc(d: dict) -> CameraDesc:
+    c = CameraDesc()
+    c.kind = _KIND[d["kind"]] if isinstance(d["kind"], str) else int(d["kind"])
+    c.W, c.H = int(d["W"]), int(d["H"])
+    c.max_level = int(d.get("max_level", -1))
+    c.level_bias = int(d.get("level_bias", 0))
+    for k in range(3):
+        c.eye[k], c.target[k], c.up[k] = d["eye"][k], d["target"][k], d["up"][k]
+    c.fov_y = float(d.get("fov_y", 0.0))
+    c.ortho_height = float(d.get("ortho_height", 0.0))
+    return c
+
+
+def set_camera(d: dict, tree: Optional[Tree] = None) -> Camera:
+    out = Camera()
+    _check(lib().amr_set_camera(ctypes.byref(camera_desc(d)), tree.handle if tree else None, ctypes.byref(out)))
+    return out
+
+
+# ---------------------------------------------------------------- render
+
+def render(tree: Tree, cam: Camera, op: int, out, aux=None, field: int = 0, weight: int = 0, los: bool = False,
+           variant: int = -1, stream=None):
+    """Enqueue one image into ``out`` (device fp32 tensor of H*W)."""
+    o = RenderOpts(field, weight, int(bool(los)), variant)
+    _check(lib().amr_render(tree.handle, ctypes.byref(cam), op, ctypes.byref(o), _ptr(out), _ptr(aux),
+                            _stream(stream)))
+    return out
+
+
+def count_segments(tree: Tree, cam: Camera, total, counts=None, stream=None):
+    """Segments per pixel (``counts``, device int32, optional) and their
+    total (``total``, device int64 of one element)."""
+    _check(lib().amr_count_segments(tree.handle, ctypes.byref(cam), _ptr(counts), _ptr(total), _stream(stream)))
+
+
+def count_rays(tree: Tree, cam: Camera, ray_ids, counts, stream=None):
+    _check(lib().amr_count_rays(tree.handle, ctypes.byref(cam), _ptr(ray_ids), int(ray_ids.numel()), _ptr(counts),
+                                _stream(stream)))
+
+
+def trace_rays(tree: Tree, cam: Camera, ray_ids, offsets, cells, stream=None):
+    _check(lib().amr_trace_rays(tree.handle, ctypes.byref(cam), _ptr(ray_ids), int(ray_ids.numel()), _ptr(offsets),
+                                _ptr(cells), _stream(stream)))
+
+
+def variants():
+    L = lib()
+    return [L.amr_variant_name(v).decode() for v in range(L.amr_variant_count())]

@@ -1,0 +1,72 @@
+"""ctypes mirror of include/amr.h (structs, enums and signatures)."""
+import ctypes
+
+AMR_OK, AMR_EINVAL, AMR_ETREE, AMR_ENOMEM, AMR_EHIP, AMR_ECAPACITY, AMR_ESTALE, AMR_EMODEL = range(8)
+STATUS_NAMES = {0: "AMR_OK", 1: "AMR_EINVAL", 2: "AMR_ETREE", 3: "AMR_ENOMEM", 4: "AMR_EHIP", 5: "AMR_ECAPACITY",
+                6: "AMR_ESTALE", 7: "AMR_EMODEL"}
+AMR_SUM, AMR_MAX, AMR_WMEAN = 0, 1, 2
+AMR_HOST, AMR_DEVICE = 0, 1
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+
+
+class LeavesC(ctypes.Structure):
+    _fields_ = [("n", _i64), ("level", _vp), ("ix", _vp), ("iy", _vp), ("iz", _vp), ("fields", _vp),
+                ("nfields", _i32), ("location", _i32), ("field_stride", _i64)]
+
+
+class BuildOpts(ctypes.Structure):
+    _fields_ = [("restrict_weight", _i32 * 8), ("use_defaults", _i32), ("host_only", _i32)]
+
+
+class TreeInfo(ctypes.Structure):
+    _fields_ = [("ncells", _i64), ("nleaves", _i64), ("nfields", _i32), ("lmax", _i32), ("levelmin", _i32),
+                ("host_only", _i32), ("cells_per_level", _i64 * 25), ("level_offset", _i64 * 26),
+                ("device_bytes", _i64)]
+
+
+class CameraDesc(ctypes.Structure):
+    _fields_ = [("kind", _i32), ("W", _i32), ("H", _i32), ("max_level", _i32), ("level_bias", _i32),
+                ("pad_", _i32), ("eye", ctypes.c_double * 3), ("target", ctypes.c_double * 3),
+                ("up", ctypes.c_double * 3), ("fov_y", ctypes.c_double), ("ortho_height", ctypes.c_double)]
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("kind", _i32), ("W", _i32), ("H", _i32), ("max_level", _i32), ("O", _i64 * 3), ("F", _i64 * 3),
+                ("U", _i64 * 3), ("V", _i64 * 3)]
+
+    def as_dict(self):
+        return dict(kind=self.kind, W=self.W, H=self.H, max_level=self.max_level, O=list(self.O), F=list(self.F),
+                    U=list(self.U), V=list(self.V))
+
+
+class RenderOpts(ctypes.Structure):
+    _fields_ = [("field", _i32), ("weight_field", _i32), ("los_velocity", _i32), ("variant", _i32)]
+
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "amr_last_error": (ctypes.c_char_p, []),
+    "amr_build_linear_octree": (_i32, [ctypes.POINTER(LeavesC), ctypes.POINTER(BuildOpts), _vp,
+                                       ctypes.POINTER(_vp)]),
+    "amr_tree_free": (None, [_vp]),
+    "amr_tree_info": (_i32, [_vp, ctypes.POINTER(TreeInfo)]),
+    "amr_tree_arrays": (_i32, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
+    "amr_set_camera": (_i32, [ctypes.POINTER(CameraDesc), _vp, ctypes.POINTER(Camera)]),
+    "amr_render": (_i32, [_vp, ctypes.POINTER(Camera), _i32, ctypes.POINTER(RenderOpts), _vp, _vp, _vp]),
+    "amr_variant_count": (_i32, []),
+    "amr_variant_name": (ctypes.c_char_p, [_i32]),
+    "amr_count_segments": (_i32, [_vp, ctypes.POINTER(Camera), _vp, _vp, _vp]),
+    "amr_trace_rays": (_i32, [_vp, ctypes.POINTER(Camera), _vp, _i64, _vp, _vp, _vp]),
+    "amr_count_rays": (_i32, [_vp, ctypes.POINTER(Camera), _vp, _i64, _vp, _vp]),
+}
+
+
+def declare(lib):
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib

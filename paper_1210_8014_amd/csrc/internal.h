@@ -1,0 +1,57 @@
+// internal.h -- library-private declarations shared by the host builder and
+// the HIP kernels.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/amr.h"
+#include "traverse.h"
+
+struct amr_tree {
+  amr::TreeView view;       // device (or host, when host_only) pointers
+  amr_tree_info_t info;
+  int32_t* d_child = nullptr;
+  float* d_val = nullptr;
+  uint8_t* d_maxdepth = nullptr;
+  // host copies kept only for host_only trees
+  std::vector<int32_t> h_child;
+  std::vector<float> h_val;
+  std::vector<uint8_t> h_maxdepth;
+  uint64_t serial = 0;      // unique id (batches detect freed trees)
+};
+
+namespace amr {
+
+void set_error(const std::string& msg);
+amr_status fail(amr_status st, const std::string& msg);
+
+CameraView camera_view(const amr_camera& c);
+
+struct RenderArgs {
+  TreeView t;
+  CameraView c;
+  int32_t field, wfield, los, max_level;
+  float* out;
+  float* aux;
+  int32_t packets_x, packets_y;
+};
+
+// Kernel launchers (render.hip).  Return a hipError_t as int.
+int launch_render(int op, int variant, const RenderArgs& a, void* stream);
+int launch_count_all(const TreeView& t, const CameraView& c, int32_t* counts, int64_t* total, void* stream);
+int launch_rays(const TreeView& t, const CameraView& c, const int64_t* ray_ids, int64_t n, const int64_t* offsets,
+                int32_t* cells, int32_t* counts, void* stream);
+int variant_count();
+const char* variant_name(int v);
+int variant_packet_width(int v);
+
+// HIP runtime wrappers (render.hip) so the host builder needs no HIP headers.
+int dev_malloc(void** p, size_t bytes);
+int dev_free(void* p);
+int dev_upload(void* dst, const void* src, size_t bytes);
+int dev_download(void* dst, const void* src, size_t bytes);
+const char* dev_error_string(int err);
+
+}  // namespace amr

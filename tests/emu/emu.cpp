@@ -1,0 +1,87 @@
+// CPU build of the library's per-ray traversal core (traverse.h), for tests
+// only: it runs the exact code the HIP kernels run, on host memory, so that
+// indexing, termination and exactness are checked on the CPU.  It is not part
+// of the product and is never loaded by it.
+#include <cstdint>
+#include <thread>
+#include <vector>
+
+#include "../../paper_1210_8014_amd/csrc/traverse.h"
+
+using namespace amr;
+
+static TreeView make_tree(const int32_t* child, const float* val, int64_t ncells, int32_t nfields, int32_t base,
+                          int32_t lmax, const int32_t* off) {
+  TreeView T{};
+  T.child = child;
+  T.val = val;
+  T.maxdepth = nullptr;
+  T.ncells = ncells;
+  T.nfields = nfields;
+  T.base = base;
+  T.lmax = lmax;
+  for (int l = 0; l < kMaxLevel + 2; ++l) T.off[l] = off[l];
+  return T;
+}
+
+static CameraView make_cam(const int32_t* k4, const int64_t* ofuv) {
+  CameraView C{};
+  C.kind = k4[0];
+  C.W = k4[1];
+  C.H = k4[2];
+  C.max_level = k4[3];
+  for (int k = 0; k < 3; ++k) {
+    C.O[k] = ofuv[k];
+    C.F[k] = ofuv[3 + k];
+    C.U[k] = ofuv[6 + k];
+    C.V[k] = ofuv[9 + k];
+  }
+  return C;
+}
+
+template <class F>
+static void par(int64_t n, F fn) {
+  int nt = std::max(1u, std::thread::hardware_concurrency());
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t)
+    th.emplace_back([=]() {
+      for (int64_t r = n * t / nt; r < n * (t + 1) / nt; ++r) fn(r);
+    });
+  for (auto& t : th) t.join();
+}
+
+extern "C" {
+
+// pix: pixel ids (j*W + i); out/aux/counts indexed like pix.
+int emu_render(const int32_t* child, const float* val, int64_t ncells, int32_t nfields, int32_t base, int32_t lmax,
+               const int32_t* off, const int32_t* cam4, const int64_t* ofuv, int32_t op, int32_t field,
+               int32_t wfield, int32_t los, int32_t max_level, const int64_t* pix, int64_t n, float* out, float* aux,
+               int32_t* counts) {
+  const TreeView T = make_tree(child, val, ncells, nfields, base, lmax, off);
+  const CameraView C = make_cam(cam4, ofuv);
+  par(n, [&](int64_t r) {
+    const int i = (int)(pix[r] % C.W), j = (int)(pix[r] / C.W);
+    float o = 0.0f, x = 0.0f;
+    if (op == 0) render_pixel<kOpSum>(T, C, field, wfield, los, max_level, i, j, o, x);
+    else if (op == 1) render_pixel<kOpMax>(T, C, field, wfield, los, max_level, i, j, o, x);
+    else render_pixel<kOpWMean>(T, C, field, wfield, los, max_level, i, j, o, x);
+    if (out) out[r] = o;
+    if (aux) aux[r] = x;
+    if (counts) counts[r] = trace_pixel(T, C, max_level, i, j, nullptr, 0);
+  });
+  return 0;
+}
+
+// offsets[n+1] must hold the prefix sum of the counts.
+int emu_trace(const int32_t* child, const float* val, int64_t ncells, int32_t nfields, int32_t base, int32_t lmax,
+              const int32_t* off, const int32_t* cam4, const int64_t* ofuv, int32_t max_level, const int64_t* pix,
+              int64_t n, const int64_t* offsets, int32_t* cells) {
+  const TreeView T = make_tree(child, val, ncells, nfields, base, lmax, off);
+  const CameraView C = make_cam(cam4, ofuv);
+  par(n, [&](int64_t r) {
+    const int i = (int)(pix[r] % C.W), j = (int)(pix[r] / C.W);
+    trace_pixel(T, C, max_level, i, j, cells + 4 * offsets[r], offsets[r + 1] - offsets[r]);
+  });
+  return 0;
+}
+}

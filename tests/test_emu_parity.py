@@ -1,0 +1,94 @@
+"""The library's traversal core (traverse.h) compiled for the CPU against the
+oracle.  Same code as the HIP kernels, so indexing, termination, exactness
+and accuracy are checked here before any GPU run; the GPU parity tests repeat
+the comparison through the HIP library."""
+import numpy as np
+import pytest
+
+import amrgen
+import oracle
+import paper_1210_8014_amd as amr
+from tests import emu
+from tests import parity
+from tests.test_oracle_pins import degenerate_cams, rand_cams
+
+
+class EmuRenderer:
+    def __init__(self, leaves, restrict=None):
+        self.T = amr.Tree(leaves, restrict=restrict, host_only=True)
+        self.E = emu.EmuTree(self.T)
+
+    def camera(self, d):
+        return amr.set_camera(d, self.T)
+
+    def render(self, cam, op, field=0, weight=0, los=False, rays=None):
+        return self.E.render(cam, op, field, weight, los, rays)
+
+    def trace(self, cam, rays):
+        return self.E.trace(cam, rays)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_trees_all_cameras(seed):
+    rng = np.random.default_rng(seed)
+    L = amrgen.random_tree(200 + seed, lmax=5, p_refine=0.45, nfields=4)
+    L.fields[1:] -= 5.0
+    R = EmuRenderer(L)
+    OT = oracle.Tree(L)
+    cams = rand_cams(rng, 8, W=9, H=7, inside=(seed % 2 == 1)) + degenerate_cams()
+    for camd in cams:
+        for ml in (OT.lmax, 2):
+            d = dict(camd, max_level=ml)
+            n = d["W"] * d["H"]
+            parity.compare_all(R, OT, d, ops=("sum", "max", "wmean"), los_fields=(1, 0, True),
+                               trace_rays=np.arange(n), what=f"seed{seed} {d['kind']} ml{ml}")
+
+
+def test_tiny_scene_full_image():
+    L = amrgen.scene("tiny")
+    R = EmuRenderer(L)
+    OT = oracle.Tree(L)
+    res = parity.compare_all(R, OT, amrgen.tiny_camera(), ops=("sum", "max"),
+                             trace_rays=np.arange(0, 65536, 7), what="tiny")
+    assert res["sum"] < 5e-7
+
+
+def test_tiny_scene_every_truncation_level():
+    L = amrgen.scene("tiny")
+    R = EmuRenderer(L)
+    OT = oracle.Tree(L)
+    for ml in range(0, 7):
+        parity.compare_all(R, OT, amrgen.tiny_camera(64, 64, max_level=ml), ops=("sum", "max"),
+                           trace_rays=np.arange(64 * 64), what=f"tiny L{ml}")
+
+
+def test_small_disk_perspective_wmean():
+    """Disk recipe at reduced depth (levels 7..11) with the three inclinations."""
+    L = amrgen.disk(seed=3, lmax=11, m_thr=2e-4)
+    assert 300_000 < L.n < 3_000_000
+    R = EmuRenderer(L)
+    OT = oracle.Tree(L)
+    rays = np.random.default_rng(0).choice(128 * 128, 3000, replace=False)
+    for cam in amrgen.disk_cameras(128, 128, max_level=11):
+        parity.compare_all(R, OT, cam, ops=("sum", "max", "wmean"), rays=rays, los_fields=(1, 0, True),
+                           trace_rays=rays[:300], what="disk")
+
+
+def test_deep_levels_fp64_boundaries():
+    """Cores refine to level 20; a camera inside the disk looks at core 0 with
+    the automatic maximum level, so cells at levels >= 18 are crossed."""
+    m_thr = 3e-3
+    L = amrgen.generate(amrgen.DISK, 0, 7, 20, m_thr, True, False)
+    assert L.lmax == 20
+    R = EmuRenderer(L)
+    OT = oracle.Tree(L)
+    tgt = amrgen.core_position(0, 20, m_thr, 0)
+    s = 2.0 ** -13
+    cam = amrgen.camera("persp", (tgt[0], tgt[1] - 0.8 * s, tgt[2] + 0.6 * s), tgt, (0, 0.6, 0.8), 96, 96,
+                        fov_y=0.9, max_level=-1)
+    c = R.camera(cam)
+    assert c.max_level >= 18
+    rays = np.arange(96 * 96)
+    offs, cells = R.trace(c, rays[::5])
+    assert cells[:, 0].max() >= 18
+    parity.compare_all(R, OT, cam, ops=("sum", "max"), trace_rays=rays[::5], what="deep")

@@ -1,0 +1,160 @@
+"""GPU parity: the HIP library against the oracle on the same seeded inputs
+(bars in tests/parity.py).  Run on an MI355X: pytest -m gpu."""
+import numpy as np
+import pytest
+
+import amrgen
+import oracle
+from tests import parity
+from tests.test_oracle_pins import degenerate_cams, rand_cams
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1210_8014_amd as amr
+
+    amr.lib()
+
+
+def _R(*a, **k):
+    from tests.gpu_render import GpuRenderer
+
+    return GpuRenderer(*a, **k)
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def test_gpu_tiny_full_image_every_variant():
+    import paper_1210_8014_amd as amr
+
+    L = amrgen.scene("tiny")
+    R = _R(L)
+    OT = oracle.Tree(L)
+    camd = amrgen.tiny_camera()
+    cam, ocam = R.camera(camd), OT.camera(camd)
+    ref_s = OT.render(ocam, oracle.SUM)
+    ref_m = OT.render(ocam, oracle.MAX)["max"]
+    base = None
+    for v in range(len(amr.variants())):
+        log("tiny variant", v, amr.variants()[v])
+        s, _ = R.full(cam, amr.SUM, variant=v)
+        m, _ = R.full(cam, amr.MAX, variant=v)
+        parity.check_sum(s, ref_s["val"], f"tiny v{v}")
+        parity.check_max(m, ref_m, f"tiny v{v}")
+        if base is None:
+            base = s
+        assert np.array_equal(s.view(np.int32), base.view(np.int32)), f"variant {v} not bit-identical"
+    cnt, tot = R.counts(cam)
+    parity.check_counts(cnt, ref_s["count"], "tiny")
+    assert tot == int(ref_s["count"].sum())
+    rays = np.arange(65536)
+    offs, cells = R.trace(cam, rays)
+    ro, rc, _ = OT.trace(ocam, rays)
+    parity.check_trace(offs, cells, ro, rc, "tiny all rays")
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_gpu_random_trees_and_degenerate_rays(seed):
+    rng = np.random.default_rng(seed)
+    L = amrgen.random_tree(200 + seed, lmax=5, p_refine=0.45, nfields=4)
+    L.fields[1:] -= 5.0
+    R = _R(L)
+    OT = oracle.Tree(L)
+    for k, camd in enumerate(rand_cams(rng, 6, W=9, H=7, inside=(seed == 1)) + degenerate_cams()):
+        for ml in (OT.lmax, 2):
+            d = dict(camd, max_level=ml)
+            log("random tree", seed, "camera", k, "max_level", ml)
+            parity.compare_all(R, OT, d, ops=("sum", "max", "wmean"), los_fields=(1, 0, True),
+                               trace_rays=np.arange(d["W"] * d["H"]), what=f"seed{seed} cam{k} ml{ml}")
+
+
+def test_gpu_every_truncation_level():
+    L = amrgen.scene("tiny")
+    R = _R(L)
+    OT = oracle.Tree(L)
+    for ml in range(0, 7):
+        log("tiny max_level", ml)
+        parity.compare_all(R, OT, amrgen.tiny_camera(128, 96, max_level=ml), ops=("sum", "max"),
+                           trace_rays=np.arange(0, 128 * 96, 3), what=f"tiny L{ml}")
+
+
+def test_gpu_edge_cases():
+    L = amrgen.scene("tiny")
+    R = _R(L)
+    OT = oracle.Tree(L)
+    cams = [
+        amrgen.tiny_camera(1, 1),                                                   # one pixel
+        amrgen.tiny_camera(37, 23),                                                 # ragged packets
+        amrgen.camera("persp", (0.5, 0.5, 2.0), (0.5, 0.5, 3.0), (0, 1, 0), 33, 17, fov_y=1.0, max_level=6),  # misses
+        amrgen.camera("persp", (0.41, 0.52, 0.47), (0.9, 0.1, 0.2), (0, 1, 0), 45, 31, fov_y=1.3, max_level=6),  # inside
+        amrgen.camera("ortho", (0.5, 0.5, -0.5), (0.5, 0.5, 0.5), (0, 1, 0), 5, 5, ortho_height=1.25, max_level=6),
+    ]
+    for k, camd in enumerate(cams):
+        log("edge camera", k)
+        parity.compare_all(R, OT, camd, ops=("sum", "max"), trace_rays=np.arange(camd["W"] * camd["H"]),
+                           what=f"edge{k}")
+    out, _ = R.full(R.camera(cams[2]), 1)
+    assert np.all(np.isneginf(out))
+
+
+def test_gpu_deep_levels_fp64_boundaries():
+    m_thr = 3e-3
+    L = amrgen.generate(amrgen.DISK, 0, 7, 20, m_thr, True, False)
+    R = _R(L)
+    OT = oracle.Tree(L)
+    tgt = amrgen.core_position(0, 20, m_thr, 0)
+    s = 2.0 ** -13
+    cam = amrgen.camera("persp", (tgt[0], tgt[1] - 0.8 * s, tgt[2] + 0.6 * s), tgt, (0, 0.6, 0.8), 256, 256,
+                        fov_y=0.9, max_level=-1)
+    assert R.camera(cam).max_level >= 18
+    log("deep zoom", R.camera(cam).max_level)
+    parity.compare_all(R, OT, cam, ops=("sum", "max"), trace_rays=np.arange(0, 65536, 11), what="deep")
+
+
+def test_gpu_disk_full_size_sampled():
+    """Galaxy disk, ~20.5M leaves, levels 7..16, 2048^2 perspective cameras at
+    inclinations 0/45/90: sum and line-of-sight mass-weighted velocity on a
+    seeded 1% ray sample; cell sequences of 2000 rays; determinism; every
+    kernel variant bit-identical."""
+    import paper_1210_8014_amd as amr
+
+    log("generating disk")
+    L = amrgen.scene("disk")
+    R = _R(L)
+    OT = oracle.Tree(L)
+    n = 2048 * 2048
+    rays = np.sort(np.random.default_rng(1).choice(n, n // 100, replace=False))
+    for k, camd in enumerate(amrgen.disk_cameras()):
+        log("disk camera", k)
+        res = parity.compare_all(R, OT, camd, ops=("sum", "max", "wmean"), rays=rays, los_fields=(1, 0, True),
+                                 trace_rays=rays[::21], what=f"disk cam{k}")
+        log("  worst sum rel", res["sum"], "wmean", res["wmean"])
+    cam = R.camera(amrgen.disk_cameras()[1])
+    a, _ = R.full(cam, amr.SUM)
+    for v in range(len(amr.variants())):
+        log("disk variant", v)
+        b, _ = R.full(cam, amr.SUM, variant=v)
+        assert np.array_equal(a.view(np.int32), b.view(np.int32)), f"variant {v} differs"
+    w1, x1 = R.full(cam, amr.WMEAN, field=1, weight=0, los=True)
+    w2, x2 = R.full(cam, amr.WMEAN, field=1, weight=0, los=True)
+    assert np.array_equal(w1.view(np.int32), w2.view(np.int32)) and np.array_equal(x1, x2)
+
+
+def test_gpu_rejects_bad_arguments():
+    import paper_1210_8014_amd as amr
+
+    R = _R(amrgen.scene("tiny"))
+    cam = R.camera(amrgen.tiny_camera())
+    out = torch.empty(cam.W * cam.H, dtype=torch.float32, device="cuda")
+    for kw in (dict(field=1), dict(variant=99)):
+        with pytest.raises(amr.AmrError) as e:
+            amr.render(R.T, cam, amr.SUM, out, **kw)
+        assert e.value.status == 1

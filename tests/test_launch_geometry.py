@@ -1,0 +1,56 @@
+"""CPU check of the render kernels' grid -> pixel mapping for every variant:
+each pixel is written by exactly one lane and no lane writes outside the
+image.  Mirrors the index arithmetic of k_render (block remap over the 8
+XCDs, packets of PW x 64/PW pixels, WPB waves per block)."""
+import numpy as np
+import pytest
+
+import paper_1210_8014_amd as amr
+
+# (packet width, waves per block, XCD remap) per variant, in library order
+VARIANTS = [(8, 4, True), (8, 2, True), (8, 1, True), (8, 8, True), (16, 4, True), (32, 4, True), (8, 4, False)]
+
+
+def xcd_remap(b, nb):
+    full = nb - nb % 8
+    if b >= full:
+        return b
+    return (b % 8) * (full // 8) + b // 8
+
+
+def covered(W, H, pw, wpb, remap):
+    ph = 64 // pw
+    px, py = -(-W // pw), -(-H // ph)
+    blocks = -(-(px * py) // wpb)
+    hits = np.zeros(W * H, np.int64)
+    for b in range(blocks):
+        blk = xcd_remap(b, blocks) if remap else b
+        for w in range(wpb):
+            packet = blk * wpb + w
+            ty, tx = divmod(packet, px)
+            for lane in range(64):
+                i, j = tx * pw + lane % pw, ty * ph + lane // pw
+                if ty >= py or i >= W or j >= H:
+                    continue
+                hits[j * W + i] += 1
+    return hits
+
+
+def test_variant_table_matches_library():
+    names = amr.variants()
+    assert len(names) == len(VARIANTS)
+    for (pw, wpb, remap), n in zip(VARIANTS, names):
+        assert n.startswith(f"p{pw}x{64 // pw}_w{wpb}_")
+        assert n.endswith("xcd") == remap
+
+
+@pytest.mark.parametrize("W,H", [(1, 1), (37, 23), (64, 64), (256, 256), (130, 9), (9, 130), (517, 211)])
+def test_every_pixel_written_once(W, H):
+    for pw, wpb, remap in VARIANTS:
+        assert np.all(covered(W, H, pw, wpb, remap) == 1), (W, H, pw, wpb, remap)
+
+
+def test_xcd_remap_is_a_permutation():
+    for nb in [1, 7, 8, 9, 64, 1000, 16384, 16389]:
+        r = [xcd_remap(b, nb) for b in range(nb)]
+        assert sorted(r) == list(range(nb))
