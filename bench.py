@@ -1,0 +1,223 @@
+"""Benchmark: ray-casting throughput on the galaxy-disk workload.
+
+One step = the whole render path over one batch: the three 2048^2
+perspective cameras (inclinations 0, 45, 90 degrees) of the ~20.5M-leaf disk
+(levels 7..16), each rendered twice -- the line-of-sight column integral of
+density (sum) and the density-weighted mean line-of-sight velocity (wmean).
+Inputs are resident in HBM before timing; tree build, camera set-up and the
+segment counts used for byte accounting are outside the timed region.
+
+Prints ONE JSON line on stdout.  Timings are taken with HIP events on the
+stream the library launches on (torch's current stream).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+B_SEG = {"sum": 8, "wmean": 20}   # value(s) + own first-child word per ray-cell segment
+B_PIX = {"sum": 4, "wmean": 8}    # output plane(s) per ray
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_disk.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1210_8014_amd", "csrc", f) for f in ("render.hip", "traverse.h")]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(leaves, cams_desc, seconds_target: float = 15.0):
+    """The oracle, as is, on a seeded sample of the same rays."""
+    import numpy as np
+
+    import oracle
+
+    ot = oracle.Tree(leaves)
+    nthreads = os.cpu_count() or 1
+    rng = np.random.default_rng(7)
+    n = cams_desc[0]["W"] * cams_desc[0]["H"]
+    per_cam = n // 2
+    rays_done = 0
+    t_total = 0.0
+    for d in cams_desc:
+        cam = ot.camera(d)
+        rays = np.sort(rng.choice(n, per_cam, replace=False))
+        t0 = time.perf_counter()
+        ot.render(cam, oracle.SUM, rays=rays, nthreads=nthreads)
+        ot.render(cam, oracle.WMEAN, field=1, weight=0, los=True, rays=rays, nthreads=nthreads)
+        t_total += time.perf_counter() - t0
+        rays_done += 2 * per_cam
+        if t_total > seconds_target:
+            break
+    ot.close()
+    return dict(value=rays_done / t_total / 1e6, unit="Mrays/s", cores=nthreads, kind="oracle",
+                sample=f"half the pixels of each 2048^2 camera (seeded), sum and wmean each, cameras in turn "
+                       f"until >= {seconds_target:.0f} s; "
+                       f"{rays_done} ray renders in {t_total:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--variant", type=int, default=-1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after timing, run one 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build renders on one GPU only; multi-GPU runs are not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import amrgen
+    import paper_1210_8014_amd as amr
+
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    leaves = amrgen.scene("disk")
+    log(f"scene: {leaves.n} leaves, lmax {leaves.lmax} ({time.time() - t0:.1f} s)")
+    tree = amr.Tree(leaves)
+    log(f"tree: {tree.ncells} cells ({time.time() - t0:.1f} s)")
+    descs = amrgen.disk_cameras(2048, 2048, max_level=16)
+    cams = [amr.set_camera(d, tree) for d in descs]
+    W, H = 2048, 2048
+    npix = W * H
+    outs = [torch.empty(npix, dtype=torch.float32, device="cuda") for _ in range(len(cams) * 2)]
+    auxs = [torch.empty(npix, dtype=torch.float32, device="cuda") for _ in cams]
+
+    # exact segment counts (untimed) for the algorithmic byte count
+    tot = torch.empty(1, dtype=torch.int64, device="cuda")
+    segs = []
+    for c in cams:
+        amr.count_segments(tree, c, tot)
+        torch.cuda.synchronize()
+        segs.append(int(tot.item()))
+    log(f"segments per camera: {segs}")
+
+    stream = torch.cuda.current_stream()
+    ev = {"sum": [], "wmean": []}
+
+    def step(record: bool):
+        for k, c in enumerate(cams):
+            if record:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+            amr.render(tree, c, amr.SUM, outs[2 * k], field=0, variant=args.variant)
+            if record:
+                e1.record(stream)
+                ev["sum"].append((k, e0, e1))
+                e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e2.record(stream)
+            amr.render(tree, c, amr.WMEAN, outs[2 * k + 1], auxs[k], field=1, weight=0, los=True,
+                       variant=args.variant)
+            if record:
+                e3.record(stream)
+                ev["wmean"].append((k, e2, e3))
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_start
+
+    ms_per_step = 1e3 * t_wall / args.steps
+    rays_per_step = 2 * len(cams) * npix
+    value = rays_per_step / (t_wall / args.steps) / 1e6
+
+    kern = {}
+    for op in ("sum", "wmean"):
+        durs = [e0.elapsed_time(e1) * 1e-3 for _, e0, e1 in ev[op]]
+        byts = [segs[k] * B_SEG[op] + npix * B_PIX[op] for k, _, _ in ev[op]]
+        avg_t = sum(durs) / len(durs)
+        avg_b = sum(byts) / len(byts)
+        kern[op] = dict(avg_ms=avg_t * 1e3, alg_bytes=avg_b, gbs=avg_b / avg_t / 1e9, total_s=sum(durs),
+                        mrays=npix / avg_t / 1e6, seg_per_s=(sum(segs) / len(segs)) / avg_t)
+        log(f"{op}: avg {avg_t * 1e3:.3f} ms/launch, {kern[op]['gbs']:.0f} GB/s algorithmic, "
+            f"{kern[op]['mrays']:.0f} Mrays/s, {kern[op]['seg_per_s'] / 1e9:.1f} Gseg/s")
+    dom = max(kern, key=lambda k: kern[k]["total_s"])
+    alg_total = sum(kern[op]["alg_bytes"] for op in kern) * len(cams)
+
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("kernel_hash") == kernel_hash() and dom in tr.get("per_launch_bytes", {}):
+            traffic = tr["per_launch_bytes"][dom]
+
+    if args.calib_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        t1 = time.time()
+        cpu = cpu_baseline(leaves, descs)
+        log(f"cpu baseline: {cpu['value']:.3f} Mrays/s on {cpu['cores']} threads ({time.time() - t1:.1f} s)")
+
+    line = {
+        "metric": "Mrays/s + HBM GB/s; learned-LOD vs plain speedup at <=1e-3 rel err",
+        "value": value,
+        "unit": "Mrays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "galaxy disk (seed 0, %d leaves, levels 7-16, density + velocity), 3 perspective "
+                        "cameras 2048x2048 at inclinations 0/45/90 deg, ops sum(rho) and wmean(v_los; w=rho)"
+                        % leaves.n,
+            "leaves": int(leaves.n),
+            "cells": int(tree.ncells),
+            "rays_per_step": rays_per_step,
+            "segments_per_camera": segs,
+            "algorithmic_GB_per_step": alg_total / 1e9,
+            "algorithmic_GBs": alg_total / (t_wall / args.steps) / 1e9,
+            "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                        for k, v in kern.items()},
+            "variant": amr.variants()[max(args.variant, 0)],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_render<" + dom + ">",
+            "achieved": kern[dom]["gbs"],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": kern[dom]["gbs"] / HBM_PEAK_GBS,
+            "traffic": traffic,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
