@@ -6,9 +6,13 @@
 // Launch shape: a wave64 owns one 64-ray packet of PW x (64 / PW) adjacent
 // pixels, so neighbouring rays walk the same cells and their gathers of the
 // first-child and value arrays hit the same cache lines.  A block holds WPB
-// waves.  Blocks are dispatched round-robin over the 8 XCDs (each with its
-// own L2); the block index is remapped so every XCD renders one contiguous
-// band of packets and keeps its part of the tree in its own L2.
+// waves.  Blocks are dispatched round-robin over the 8 XCDs.  Keeping that
+// interleave (consecutive packets on different XCDs at the same time) makes
+// all XCDs walk the same region of the tree together, so the memory-side
+// Infinity Cache, shared by the XCDs, holds one working set; the optional
+// remap that gives each XCD its own band of the image (better reuse in the
+// per-XCD L2, 8 working sets at once) measured slower and is kept only as a
+// variant.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -23,8 +27,18 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return (b % 8) * (full / 8) + b / 8;
 }
 
-template <int OP, int PW, int WPB, bool REMAP>
+// Per-lane ancestor stack in LDS, laid out [level][thread] so the 64 lanes
+// of a wave touch 64 consecutive words.
+struct LdsStack {
+  int32_t* base;
+  int stride, lo;
+  __device__ int32_t get(int l) const { return base[(l - lo) * stride]; }
+  __device__ void set(int l, int32_t v) { base[(l - lo) * stride] = v; }
+};
+
+template <int OP, int PW, int WPB, bool REMAP, int MODE>
 __global__ __launch_bounds__(64 * WPB) void k_render(RenderArgs A) {
+  extern __shared__ int32_t lds[];
   constexpr int PH = 64 / PW;
   const int lane = threadIdx.x & 63;
   const int blk = REMAP ? xcd_remap((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
@@ -34,7 +48,13 @@ __global__ __launch_bounds__(64 * WPB) void k_render(RenderArgs A) {
   if (ty >= A.packets_y || i >= A.c.W || j >= A.c.H) return;
   const int64_t pix = (int64_t)j * A.c.W + i;
   float o = 0.0f, x = 0.0f;
-  render_pixel<OP>(A.t, A.c, A.field, A.wfield, A.los, A.max_level, i, j, o, x);
+  if (MODE == kWalkStack) {
+    LdsStack S{lds + threadIdx.x, (int)blockDim.x, A.t.base < A.max_level ? A.t.base : A.max_level};
+    render_pixel<OP, MODE>(A.t, A.c, A.field, A.wfield, A.los, A.max_level, i, j, o, x, S);
+  } else {
+    NoStack S;
+    render_pixel<OP, MODE>(A.t, A.c, A.field, A.wfield, A.los, A.max_level, i, j, o, x, S);
+  }
   A.out[pix] = o;
   if (OP == kOpWMean && A.aux) A.aux[pix] = x;
 }
@@ -80,37 +100,44 @@ __global__ __launch_bounds__(256) void k_rays(TreeView T, CameraView C, const in
   }
 }
 
-// Variant table: packet width, waves per block, XCD remap.
+// Variant table: packet width, waves per block, XCD remap, descent mode.
 struct Variant {
   int pw, wpb;
   bool remap;
+  int mode;
   const char* name;
 };
 constexpr Variant kVariants[] = {
-    {8, 4, true, "p8x8_w4_xcd"},  {8, 2, true, "p8x8_w2_xcd"},   {8, 1, true, "p8x8_w1_xcd"},
-    {8, 8, true, "p8x8_w8_xcd"},  {16, 4, true, "p16x4_w4_xcd"}, {32, 4, true, "p32x2_w4_xcd"},
-    {8, 4, false, "p8x8_w4_linear"},
+    {8, 1, false, kWalkFast, "p8x8_w1_fast"},   {8, 2, false, kWalkFast, "p8x8_w2_fast"},
+    {8, 4, false, kWalkFast, "p8x8_w4_fast"},   {16, 4, false, kWalkFast, "p16x4_w4_fast"},
+    {32, 2, false, kWalkFast, "p32x2_w2_fast"}, {8, 1, false, kWalkBase, "p8x8_w1_base"},
+    {8, 4, false, kWalkBase, "p8x8_w4_base"},   {8, 1, false, kWalkStack, "p8x8_w1_stack"},
+    {8, 4, true, kWalkFast, "p8x8_w4_fast_xcdband"},
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
-template <int OP, int PW, int WPB, bool REMAP>
+template <int OP, int PW, int WPB, bool REMAP, int MODE>
 hipError_t launch_one(const RenderArgs& a, hipStream_t s) {
   const int64_t packets = (int64_t)a.packets_x * a.packets_y;
   const int64_t blocks = (packets + WPB - 1) / WPB;
-  hipLaunchKernelGGL((k_render<OP, PW, WPB, REMAP>), dim3((unsigned)blocks), dim3(64 * WPB), 0, s, a);
+  const int b0 = a.t.base < a.max_level ? a.t.base : a.max_level;
+  const size_t lds = MODE == kWalkStack ? (size_t)(a.max_level - b0 + 1) * 64 * WPB * sizeof(int32_t) : 0;
+  hipLaunchKernelGGL((k_render<OP, PW, WPB, REMAP, MODE>), dim3((unsigned)blocks), dim3(64 * WPB), lds, s, a);
   return hipGetLastError();
 }
 
 template <int OP>
 hipError_t launch_op(int v, const RenderArgs& a, hipStream_t s) {
   switch (v) {
-    case 0: return launch_one<OP, 8, 4, true>(a, s);
-    case 1: return launch_one<OP, 8, 2, true>(a, s);
-    case 2: return launch_one<OP, 8, 1, true>(a, s);
-    case 3: return launch_one<OP, 8, 8, true>(a, s);
-    case 4: return launch_one<OP, 16, 4, true>(a, s);
-    case 5: return launch_one<OP, 32, 4, true>(a, s);
-    case 6: return launch_one<OP, 8, 4, false>(a, s);
+    case 0: return launch_one<OP, 8, 1, false, kWalkFast>(a, s);
+    case 1: return launch_one<OP, 8, 2, false, kWalkFast>(a, s);
+    case 2: return launch_one<OP, 8, 4, false, kWalkFast>(a, s);
+    case 3: return launch_one<OP, 16, 4, false, kWalkFast>(a, s);
+    case 4: return launch_one<OP, 32, 2, false, kWalkFast>(a, s);
+    case 5: return launch_one<OP, 8, 1, false, kWalkBase>(a, s);
+    case 6: return launch_one<OP, 8, 4, false, kWalkBase>(a, s);
+    case 7: return launch_one<OP, 8, 1, false, kWalkStack>(a, s);
+    case 8: return launch_one<OP, 8, 4, true, kWalkFast>(a, s);
     default: return hipErrorInvalidValue;
   }
 }

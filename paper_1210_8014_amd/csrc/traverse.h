@@ -97,6 +97,9 @@ AMR_HD uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
 }
 
 AMR_HD int64_t mul64(int32_t a, int32_t b) { return (int64_t)a * (int64_t)b; }
+#if !defined(__HIPCC__)
+inline int min(int a, int b) { return a < b ? a : b; }
+#endif
 
 AMR_HD void kahan_add(float& s, float& c, float x) {
   float y = x - c;
@@ -122,9 +125,10 @@ struct Ray {
   double ulen64;   // |d| 2^-28
 };
 
-// Entry point of the current cell: t = (Xa - oa) / da on axis a, or t = 0
-// (a < 0) when the ray starts inside the box.  p[] holds the integer part
-// of the entry point (mirrored), exactly on the axes flagged in `exact`,
+// Entry point of the current cell: parameter t = (Xa - oa) / da, the
+// crossing of plane Xa on axis a; a < 0 when the ray starts inside the box
+// (then Xa = oa = 0, da = 1, so t = 0).  p[] holds the integer part of the
+// entry point (mirrored), exact on the axes flagged in `exact` and known
 // down to level `lam` on the others.
 struct Entry {
   int32_t p[3];
@@ -133,11 +137,6 @@ struct Entry {
   float inv_da;
   int exact, lam;
 };
-
-template <class T>
-AMR_HD T sel3(const T (&v)[3], int k) {
-  return k == 0 ? v[0] : (k == 1 ? v[1] : v[2]);
-}
 
 // Builds the integer ray of pixel (i, j) and clips it to the box.  Returns
 // false if the ray spends no positive length inside the box.
@@ -202,8 +201,8 @@ AMR_HD bool setup_ray(const CameraView& C, int i, int j, Ray& R, Entry& E) {
   }
   E.a = a;
   E.Xa = 0;
-  E.oa = oa;
-  E.da = ed;
+  E.oa = oa;  // 0 when a < 0
+  E.da = ed;  // 1 when a < 0
   E.exact = 7;
   E.lam = kFix;
   // chord scale factors
@@ -215,29 +214,69 @@ AMR_HD bool setup_ray(const CameraView& C, int i, int j, Ray& R, Entry& E) {
     R.inv_d[k] = R.d[k] > 0 ? 1.0f / (float)R.d[k] : 0.0f;
     R.wk[k] = R.d[k] > 0 ? ulen / (float)R.d[k] : 0.0f;
   }
-  E.inv_da = a < 0 ? 0.0f : 1.0f / (float)ed;
+  E.inv_da = a < 0 ? 1.0f : 1.0f / (float)ed;
   return true;
 }
 
-// Walks the cells of one ray.  The visitor sees, for every cell met, its
-// index, level, chord length and mirrored cell coordinates:
-//   vis.seg(node, level, len, cm0, cm1, cm2)
-// It returns the number of cells visited.  max_level truncates the tree.
-template <class Vis>
-AMR_HD int32_t walk_ray(const TreeView& T, const Ray& R, Entry& E, int max_level, Vis& vis) {
+// int64 -> fp32 as hi * 2^32 + lo in one fused step (identical on host and
+// device; at most ~1.5 ulp from the correctly rounded conversion).
+AMR_HD float i64_to_f32(int64_t v) {
+  const int32_t hi = (int32_t)(v >> 32);
+  const uint32_t lo = (uint32_t)(v & 0xffffffffu);
+  return fmaf((float)hi, 4294967296.0f, (float)lo);
+}
+
+// Ancestor stack for the restart-from-common-ancestor descent: slot l holds
+// the first-child index of the current path's cell at level l.
+struct NoStack {
+  AMR_HD int32_t get(int) const { return 0; }
+  AMR_HD void set(int, int32_t) {}
+};
+struct LocalStack {  // host builds
+  int32_t w[kMaxLevel + 1];
+  AMR_HD int32_t get(int l) const { return w[l]; }
+  AMR_HD void set(int l, int32_t v) { w[l] = v; }
+};
+
+// Walks the cells of one ray.  For every cell met, the visitor's
+//   fetch(node)        is called as soon as the cell is located, and
+//   seg(node, level, len, cm0, cm1, cm2)  once its chord is known
+// (cm = mirrored cell coordinates).  Returns the number of cells.
+// LCA = false restarts every descent at the complete base level; LCA = true
+// restarts at the deepest ancestor shared with the previous cell, whose
+// first-child index is kept in the stack S.  Both meet exactly the same cells
+// and compute exactly the same chords.
+template <bool LCA, class Vis, class Stack>
+AMR_HD int32_t walk(const TreeView& T, const Ray& R, Entry& E, int max_level, Vis& vis, Stack& S) {
   const int b0 = T.base < max_level ? T.base : max_level;
+  // virtual direction for axes that do not move: their exit never wins
+  const int32_t dv0 = R.d[0] > 0 ? R.d[0] : 1, dv1 = R.d[1] > 0 ? R.d[1] : 1, dv2 = R.d[2] > 0 ? R.d[2] : 1;
+  const float wk0 = R.wk[0], wk1 = R.wk[1], wk2 = R.wk[2];
+  const float iv0 = R.inv_d[0], iv1 = R.inv_d[1], iv2 = R.inv_d[2];
   int32_t nseg = 0;
+  int jr = -1;  // restart level (LCA only): the stack holds levels b0..jr of the entry point's path
   for (;;) {
     // ---- locate the cell containing r(t_entry + 0)
-    int lvl = b0;
-    const int sb = kFix - b0;
-    int32_t node = T.off[b0] + (int32_t)morton3((uint32_t)((E.p[0] ^ R.flip[0]) >> sb),
-                                                (uint32_t)((E.p[1] ^ R.flip[1]) >> sb),
-                                                (uint32_t)((E.p[2] ^ R.flip[2]) >> sb));
+    int lvl;
+    int32_t node;
+    if (!LCA || jr < b0) {
+      lvl = b0;
+      const int sb = kFix - b0;
+      node = T.off[b0] + (int32_t)morton3((uint32_t)((E.p[0] ^ R.flip[0]) >> sb),
+                                          (uint32_t)((E.p[1] ^ R.flip[1]) >> sb),
+                                          (uint32_t)((E.p[2] ^ R.flip[2]) >> sb));
+    } else {
+      lvl = jr + 1;  // bits down to lvl are known: jr < level of the previous cell
+      const int s = kFix - lvl;
+      const int oct = (((E.p[0] ^ R.flip[0]) >> s) & 1) | ((((E.p[1] ^ R.flip[1]) >> s) & 1) << 1) |
+                      ((((E.p[2] ^ R.flip[2]) >> s) & 1) << 2);
+      node = S.get(jr) + oct;
+    }
     AMR_CHECK_CELL(T, node);
     while (lvl < max_level) {
       const int32_t w = T.child[node];
       if (w < 0) break;
+      if (LCA) S.set(lvl, w);
       ++lvl;
       const int s = kFix - lvl;
       if (lvl > E.lam) {
@@ -256,65 +295,61 @@ AMR_HD int32_t walk_ray(const TreeView& T, const Ray& R, Entry& E, int max_level
       node = w + oct;
       AMR_CHECK_CELL(T, node);
     }
-    // ---- exit face: smallest (X_k - o_k) / d_k over moving axes, ties kept
+    vis.fetch(node);
+    // ---- exit face: smallest (X_k - o_k) / d_k, ties kept (branch-free;
+    // plain scalars, so no select is folded into an indexed load)
     const int s = kFix - lvl;
-    int32_t X[3];
-    int best = -1, tie = 0;
-    int32_t nb = 0, db = 1, Xb = 0;
-    float wkb = 0.0f, invb = 0.0f;
-    AMR_UNROLL
-    for (int k = 0; k < 3; ++k) {
-      X[k] = ((E.p[k] >> s) + 1) << s;
-      if (R.d[k] == 0) continue;
-      const int32_t nk = X[k] - R.o[k];
-      bool take = best < 0;
-      if (!take) {
-        const int64_t diff = mul64(nk, db) - mul64(nb, R.d[k]);
-        if (diff == 0) tie |= 1 << k;
-        take = diff < 0;
-      }
-      if (take) {
-        best = k;
-        tie = 1 << k;
-        nb = nk;
-        db = R.d[k];
-        Xb = X[k];
-        wkb = R.wk[k];
-        invb = R.inv_d[k];
-      }
-    }
-    // ---- chord length from the exact numerator of t_exit - t_entry
+    const int32_t X0 = ((E.p[0] >> s) + 1) << s;
+    const int32_t X1 = ((E.p[1] >> s) + 1) << s;
+    const int32_t X2 = ((E.p[2] >> s) + 1) << s;
+    const int32_t n0 = R.d[0] > 0 ? X0 - R.o[0] : 0x7fffffff;
+    const int32_t n1 = R.d[1] > 0 ? X1 - R.o[1] : 0x7fffffff;
+    const int32_t n2 = R.d[2] > 0 ? X2 - R.o[2] : 0x7fffffff;
+    const int64_t c01 = mul64(n0, dv1) - mul64(n1, dv0);  // sign of t0 - t1
+    const bool p1 = c01 > 0;
+    const int32_t nA = p1 ? n1 : n0, dA = p1 ? dv1 : dv0;
+    const int tieA = c01 == 0 ? 3 : (p1 ? 2 : 1);
+    const int64_t c2 = mul64(nA, dv2) - mul64(n2, dA);  // sign of tA - t2
+    const bool p2 = c2 > 0;
+    const int best = p2 ? 2 : (p1 ? 1 : 0);
+    const int tie = p2 ? 4 : (c2 == 0 ? (tieA | 4) : tieA);
+    const int32_t nb = p2 ? n2 : nA;
+    const int32_t db = p2 ? dv2 : dA;
+    const int32_t Xb = p2 ? X2 : (p1 ? X1 : X0);
+    const float wkb = p2 ? wk2 : (p1 ? wk1 : wk0);
+    const float invb = p2 ? iv2 : (p1 ? iv1 : iv0);
+    // ---- chord from the exact numerator of (t_exit - t_entry) d_a d_b
+    const int64_t N = mul64(nb, E.da) - mul64(E.Xa - E.oa, db);
     float len;
-    if (lvl < kDeepLevel) {
-      if (E.a < 0)
-        len = (float)nb * wkb;
-      else if (E.a == best)
-        len = (float)(Xb - E.Xa) * wkb;
-      else
-        len = (float)(mul64(nb, E.da) - mul64(E.Xa - E.oa, db)) * wkb * E.inv_da;
-    } else {
-      double l64;
-      if (E.a < 0)
-        l64 = (double)nb * R.ulen64 / (double)db;
-      else if (E.a == best)
-        l64 = (double)(Xb - E.Xa) * R.ulen64 / (double)db;
-      else
-        l64 = (double)(mul64(nb, E.da) - mul64(E.Xa - E.oa, db)) * R.ulen64 / ((double)E.da * (double)db);
-      len = (float)l64;
-    }
+    if (lvl < kDeepLevel)
+      len = i64_to_f32(N) * wkb * E.inv_da;
+    else
+      len = (float)((double)N * R.ulen64 / ((double)E.da * (double)db));
     vis.seg(node, lvl, len, E.p[0] >> s, E.p[1] >> s, E.p[2] >> s);
     ++nseg;
     // ---- leave the box, or enter the neighbour
-    bool out = false;
-    AMR_UNROLL
-    for (int k = 0; k < 3; ++k)
-      if ((tie & (1 << k)) && X[k] == kOne) out = true;
+    const bool out = ((tie & 1) && X0 == kOne) || ((tie & 2) && X1 == kOne) || ((tie & 4) && X2 == kOne);
     if (out) break;
+    if (LCA) {
+      // deepest level whose cell still contains the new entry point: a tied
+      // axis whose level-lvl coordinate ends in t one-bits carries t+1 levels up
+      jr = lvl - 1;
+      AMR_UNROLL
+      for (int k = 0; k < 3; ++k) {
+        if (tie & (1 << k)) {
+          const uint32_t c = (uint32_t)(E.p[k] >> s);
+          const int t1 = __builtin_ctz(~c);
+          const int j = lvl - t1 - 1;
+          jr = j < jr ? j : jr;
+        }
+      }
+    }
     const int32_t keep = ~((int32_t(1) << s) - 1);
+    const int32_t Xs[3] = {X0, X1, X2};
     AMR_UNROLL
     for (int k = 0; k < 3; ++k) {
       if (tie & (1 << k)) {
-        E.p[k] = X[k];
+        E.p[k] = Xs[k];
         E.exact |= 1 << k;
       } else if (R.d[k] > 0) {
         E.p[k] &= keep;
@@ -331,21 +366,169 @@ AMR_HD int32_t walk_ray(const TreeView& T, const Ray& R, Entry& E, int max_level
   return nseg;
 }
 
+// Morton-code step of one complete-level cell along axis k (0, 1, 2) by
+// +1 or -1, on a 30-bit code (dilated-integer add / subtract).
+AMR_HD uint32_t morton_step(uint32_t m, int k, bool down) {
+  const uint32_t mk = 0x09249249u << k;
+  const uint32_t nk = down ? (((m & mk) - (1u << k)) & mk) : (((m | ~mk) + (1u << k)) & mk);
+  return (m & ~mk) | nk;
+}
+
+// The same walk as walk<false> (identical cells, chords and order), with
+// less work per cell:
+//  - the Morton index of the complete-level cell is stepped along the axes
+//    whose base-level coordinate changes instead of being recomputed;
+//  - the first-child index of the current cell's parent stays in a
+//    register, so moving to a sibling (about half of all moves) skips the
+//    descent from the base level;
+//  - the unmirrored coordinates are formed once per cell, not per level;
+//  - visitors that do not use chord lengths skip their arithmetic.
+template <class Vis>
+AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_level, Vis& vis) {
+  const int b0 = T.base < max_level ? T.base : max_level;
+  const int sb = kFix - b0;
+  const int32_t dv0 = R.d[0] > 0 ? R.d[0] : 1, dv1 = R.d[1] > 0 ? R.d[1] : 1, dv2 = R.d[2] > 0 ? R.d[2] : 1;
+  const float wk0 = R.wk[0], wk1 = R.wk[1], wk2 = R.wk[2];
+  const float iv0 = R.inv_d[0], iv1 = R.inv_d[1], iv2 = R.inv_d[2];
+  const int32_t f0 = R.flip[0], f1 = R.flip[1], f2 = R.flip[2];
+  uint32_t mb = morton3((uint32_t)((E.p[0] ^ f0) >> sb), (uint32_t)((E.p[1] ^ f1) >> sb),
+                        (uint32_t)((E.p[2] ^ f2) >> sb));
+  int32_t pfc = -1;  // first-child index of the current cell's parent (-1: none cached)
+  int plv = -1;      // level of that parent
+  int jr = -1;       // restart level
+  int32_t nseg = 0;
+  for (;;) {
+    uint32_t q0 = (uint32_t)(E.p[0] ^ f0), q1 = (uint32_t)(E.p[1] ^ f1), q2 = (uint32_t)(E.p[2] ^ f2);
+    int lvl;
+    int32_t node;
+    if (jr >= 0 && jr == plv) {
+      lvl = jr + 1;  // sibling of the previous cell
+      const int s = kFix - lvl;
+      node = pfc + (int32_t)(((q0 >> s) & 1u) | (((q1 >> s) & 1u) << 1) | (((q2 >> s) & 1u) << 2));
+    } else {
+      lvl = b0;
+      node = T.off[b0] + (int32_t)mb;
+      pfc = -1;
+      plv = -1;
+    }
+    AMR_CHECK_CELL(T, node);
+    while (lvl < max_level) {
+      const int32_t w = T.child[node];
+      if (w < 0) break;
+      pfc = w;
+      plv = lvl;
+      ++lvl;
+      const int s = kFix - lvl;
+      if (lvl > E.lam) {
+        AMR_UNROLL
+        for (int k = 0; k < 3; ++k) {
+          if (E.exact & (1 << k)) continue;
+          const int32_t M = E.p[k] + (int32_t(1) << s);
+          if (mul64(E.Xa - E.oa, R.d[k]) >= mul64(M - R.o[k], E.da)) E.p[k] = M;
+        }
+        E.lam = lvl;
+        q0 = (uint32_t)(E.p[0] ^ f0);
+        q1 = (uint32_t)(E.p[1] ^ f1);
+        q2 = (uint32_t)(E.p[2] ^ f2);
+      }
+      node = w + (int32_t)(((q0 >> s) & 1u) | (((q1 >> s) & 1u) << 1) | (((q2 >> s) & 1u) << 2));
+      AMR_CHECK_CELL(T, node);
+    }
+    vis.fetch(node);
+    const int s = kFix - lvl;
+    const int32_t low = (int32_t(1) << s) - 1;
+    const int32_t X0 = (E.p[0] | low) + 1, X1 = (E.p[1] | low) + 1, X2 = (E.p[2] | low) + 1;
+    const int32_t n0 = R.d[0] > 0 ? X0 - R.o[0] : 0x7fffffff;
+    const int32_t n1 = R.d[1] > 0 ? X1 - R.o[1] : 0x7fffffff;
+    const int32_t n2 = R.d[2] > 0 ? X2 - R.o[2] : 0x7fffffff;
+    const int64_t c01 = mul64(n0, dv1) - mul64(n1, dv0);
+    const bool p1 = c01 > 0;
+    const int32_t nA = p1 ? n1 : n0, dA = p1 ? dv1 : dv0;
+    const int tieA = c01 == 0 ? 3 : (p1 ? 2 : 1);
+    const int64_t c2 = mul64(nA, dv2) - mul64(n2, dA);
+    const bool p2 = c2 > 0;
+    const int best = p2 ? 2 : (p1 ? 1 : 0);
+    const int tie = p2 ? 4 : (c2 == 0 ? (tieA | 4) : tieA);
+    const int32_t nb = p2 ? n2 : nA;
+    const int32_t db = p2 ? dv2 : dA;
+    const int32_t Xb = p2 ? X2 : (p1 ? X1 : X0);
+    const float invb = p2 ? iv2 : (p1 ? iv1 : iv0);
+    float len = 0.0f;
+    if (Vis::kNeedsLength) {
+      const float wkb = p2 ? wk2 : (p1 ? wk1 : wk0);
+      const int64_t N = mul64(nb, E.da) - mul64(E.Xa - E.oa, db);
+      if (lvl < kDeepLevel)
+        len = i64_to_f32(N) * wkb * E.inv_da;
+      else
+        len = (float)((double)N * R.ulen64 / ((double)E.da * (double)db));
+    }
+    vis.seg(node, lvl, len, E.p[0] >> s, E.p[1] >> s, E.p[2] >> s);
+    ++nseg;
+    const bool t0 = tie & 1, t1 = tie & 2, t2 = tie & 4;
+    if ((t0 && X0 == kOne) || (t1 && X1 == kOne) || (t2 && X2 == kOne)) break;
+    // restart level and base-cell steps: a tied axis whose coordinate at this
+    // level ends in r one-bits carries r + 1 levels up
+    const int span = lvl - b0;
+    const int32_t bmask = (int32_t(1) << span) - 1;
+    jr = lvl - 1;
+    if (t0) {
+      const int32_t c = E.p[0] >> s;
+      jr = min(jr, lvl - 1 - (int)__builtin_ctz(~(uint32_t)c));
+      if (((c + 1) & bmask) == 0) mb = morton_step(mb, 0, f0 != 0);
+    }
+    if (t1) {
+      const int32_t c = E.p[1] >> s;
+      jr = min(jr, lvl - 1 - (int)__builtin_ctz(~(uint32_t)c));
+      if (((c + 1) & bmask) == 0) mb = morton_step(mb, 1, f1 != 0);
+    }
+    if (t2) {
+      const int32_t c = E.p[2] >> s;
+      jr = min(jr, lvl - 1 - (int)__builtin_ctz(~(uint32_t)c));
+      if (((c + 1) & bmask) == 0) mb = morton_step(mb, 2, f2 != 0);
+    }
+    const int32_t keep = ~low;
+    E.p[0] = t0 ? X0 : (R.d[0] > 0 ? (E.p[0] & keep) : E.p[0]);
+    E.p[1] = t1 ? X1 : (R.d[1] > 0 ? (E.p[1] & keep) : E.p[1]);
+    E.p[2] = t2 ? X2 : (R.d[2] > 0 ? (E.p[2] & keep) : E.p[2]);
+    const int moving = (R.d[0] > 0 ? 1 : 0) | (R.d[1] > 0 ? 2 : 0) | (R.d[2] > 0 ? 4 : 0);
+    E.exact = (E.exact & ~moving) | tie;
+    E.lam = lvl;
+    E.a = best;
+    E.Xa = Xb;
+    E.oa = Xb - nb;
+    E.da = db;
+    E.inv_da = invb;
+  }
+  return nseg;
+}
+
+template <class Vis>
+AMR_HD int32_t walk_ray(const TreeView& T, const Ray& R, Entry& E, int max_level, Vis& vis) {
+  NoStack S;
+  return walk<false>(T, R, E, max_level, vis, S);
+}
+
 // ----------------------------------------------------------------- visitors
 
 struct SumVis {
+  static constexpr bool kNeedsLength = true;
   const float* v;
-  float s = 0.0f, c = 0.0f;
-  AMR_HD void seg(int32_t node, int, float len, int32_t, int32_t, int32_t) { kahan_add(s, c, v[node] * len); }
+  float s = 0.0f, c = 0.0f, x = 0.0f;
+  AMR_HD void fetch(int32_t node) { x = v[node]; }
+  AMR_HD void seg(int32_t, int, float len, int32_t, int32_t, int32_t) { kahan_add(s, c, x * len); }
 };
 
 struct MaxVis {
+  static constexpr bool kNeedsLength = false;
   const float* v;
   float m;
-  AMR_HD void seg(int32_t node, int, float, int32_t, int32_t, int32_t) { m = fmaxf(m, v[node]); }
+  float x = 0.0f;
+  AMR_HD void fetch(int32_t node) { x = v[node]; }
+  AMR_HD void seg(int32_t, int, float, int32_t, int32_t, int32_t) { m = fmaxf(m, x); }
 };
 
 struct WMeanVis {
+  static constexpr bool kNeedsLength = true;
   const float* w;
   const float* f0;
   const float* f1;
@@ -353,23 +536,36 @@ struct WMeanVis {
   float dh[3];
   int los;
   float sw = 0.0f, cw = 0.0f, sf = 0.0f, cf = 0.0f;
-  AMR_HD void seg(int32_t node, int, float len, int32_t, int32_t, int32_t) {
-    const float wl = w[node] * len;
-    float f = f0[node];
-    if (los) f = f * dh[0] + f1[node] * dh[1] + f2[node] * dh[2];
+  float xw = 0.0f, x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
+  AMR_HD void fetch(int32_t node) {
+    xw = w[node];
+    x0 = f0[node];
+    if (los) {
+      x1 = f1[node];
+      x2 = f2[node];
+    }
+  }
+  AMR_HD void seg(int32_t, int, float len, int32_t, int32_t, int32_t) {
+    const float wl = xw * len;
+    float f = x0;
+    if (los) f = x0 * dh[0] + x1 * dh[1] + x2 * dh[2];
     kahan_add(sw, cw, wl);
     kahan_add(sf, cf, wl * f);
   }
 };
 
 struct CountVis {
+  static constexpr bool kNeedsLength = false;
+  AMR_HD void fetch(int32_t) {}
   AMR_HD void seg(int32_t, int, float, int32_t, int32_t, int32_t) {}
 };
 
 // Writes (level, ix, iy, iz) of every cell, unmirrored.
 struct TraceVis {
+  static constexpr bool kNeedsLength = false;
   int32_t* out;
   int32_t flip_bits[3];  // 1 on mirrored axes
+  AMR_HD void fetch(int32_t) {}
   AMR_HD void seg(int32_t, int lvl, float, int32_t c0, int32_t c1, int32_t c2) {
     const int32_t m = (int32_t(1) << lvl) - 1;
     out[0] = lvl;
@@ -386,20 +582,31 @@ enum { kOpSum = 0, kOpMax = 1, kOpWMean = 2 };
 
 // The whole per-pixel computation of one projection; out receives the
 // pixel value, aux (WMEAN) the weight integral.
-template <int OP>
+// Descent modes: restart at the complete base level (kWalkBase), at the
+// common ancestor kept in a stack (kWalkStack), or the register-cached
+// form (kWalkFast).  All three meet the same cells with the same chords.
+enum { kWalkBase = 0, kWalkStack = 1, kWalkFast = 2 };
+
+template <int MODE, class Vis, class Stack>
+AMR_HD int32_t walk_mode(const TreeView& T, const Ray& R, Entry& E, int max_level, Vis& v, Stack& S) {
+  if (MODE == kWalkFast) return walk_fast(T, R, E, max_level, v);
+  return walk<MODE == kWalkStack>(T, R, E, max_level, v, S);
+}
+
+template <int OP, int MODE, class Stack>
 AMR_HD void render_pixel(const TreeView& T, const CameraView& C, int field, int wfield, int los, int max_level,
-                         int i, int j, float& out, float& aux) {
+                         int i, int j, float& out, float& aux, Stack& S) {
   Ray R;
   Entry E;
   const bool hit = setup_ray(C, i, j, R, E);
   const int64_t nc = T.ncells;
   if (OP == kOpSum) {
     SumVis v{T.val + (int64_t)field * nc};
-    if (hit) walk_ray(T, R, E, max_level, v);
+    if (hit) walk_mode<MODE>(T, R, E, max_level, v, S);
     out = v.s - v.c;
   } else if (OP == kOpMax) {
     MaxVis v{T.val + (int64_t)field * nc, -INFINITY};
-    if (hit) walk_ray(T, R, E, max_level, v);
+    if (hit) walk_mode<MODE>(T, R, E, max_level, v, S);
     out = v.m;
   } else {
     WMeanVis v;
@@ -413,10 +620,10 @@ AMR_HD void render_pixel(const TreeView& T, const CameraView& C, int field, int 
       const float n = sqrtf((float)(R.d64[0] * R.d64[0] + R.d64[1] * R.d64[1] + R.d64[2] * R.d64[2]));
       AMR_UNROLL
       for (int k = 0; k < 3; ++k) v.dh[k] = (float)R.d64[k] / n;
-      walk_ray(T, R, E, max_level, v);
+      walk_mode<MODE>(T, R, E, max_level, v, S);
     }
-    const float W = v.sw - v.cw, S = v.sf - v.cf;
-    out = W > 0.0f ? S / W : 0.0f;
+    const float W = v.sw - v.cw, Sf = v.sf - v.cf;
+    out = W > 0.0f ? Sf / W : 0.0f;
     aux = W;
   }
 }

@@ -55,7 +55,7 @@ class EmuTree:
         return (_p(self.child), _p(self.vals), ctypes.c_int64(self.ncells), ctypes.c_int32(self.nfields),
                 ctypes.c_int32(self.base), ctypes.c_int32(self.lmax), _p(self.off))
 
-    def render(self, cam, op, field=0, weight=0, los=False, rays=None, max_level=None):
+    def render(self, cam, op, field=0, weight=0, los=False, rays=None, max_level=None, lca=2):
         n = cam.W * cam.H if rays is None else len(rays)
         pix = np.arange(n, dtype=np.int64) if rays is None else np.ascontiguousarray(rays, np.int64)
         out = np.zeros(n, np.float32)
@@ -65,7 +65,7 @@ class EmuTree:
         ml = cam.max_level if max_level is None else max_level
         _load().emu_render(*self._tree_args(), _p(k4), _p(ofuv), ctypes.c_int32(op), ctypes.c_int32(field),
                            ctypes.c_int32(weight), ctypes.c_int32(int(los)), ctypes.c_int32(ml), _p(pix),
-                           ctypes.c_int64(n), _p(out), _p(aux), _p(cnt))
+                           ctypes.c_int64(n), _p(out), _p(aux), _p(cnt), ctypes.c_int32(int(lca)))
         return out, aux, cnt
 
     def trace(self, cam, rays):

@@ -56,15 +56,27 @@ extern "C" {
 int emu_render(const int32_t* child, const float* val, int64_t ncells, int32_t nfields, int32_t base, int32_t lmax,
                const int32_t* off, const int32_t* cam4, const int64_t* ofuv, int32_t op, int32_t field,
                int32_t wfield, int32_t los, int32_t max_level, const int64_t* pix, int64_t n, float* out, float* aux,
-               int32_t* counts) {
+               int32_t* counts, int32_t lca) {
   const TreeView T = make_tree(child, val, ncells, nfields, base, lmax, off);
   const CameraView C = make_cam(cam4, ofuv);
   par(n, [&](int64_t r) {
     const int i = (int)(pix[r] % C.W), j = (int)(pix[r] / C.W);
     float o = 0.0f, x = 0.0f;
-    if (op == 0) render_pixel<kOpSum>(T, C, field, wfield, los, max_level, i, j, o, x);
-    else if (op == 1) render_pixel<kOpMax>(T, C, field, wfield, los, max_level, i, j, o, x);
-    else render_pixel<kOpWMean>(T, C, field, wfield, los, max_level, i, j, o, x);
+    LocalStack S;
+    for (int l = 0; l <= kMaxLevel; ++l) S.w[l] = -7;  // poison: a stale read shows up as a bad index
+    if (lca == 1) {
+      if (op == 0) render_pixel<kOpSum, kWalkStack>(T, C, field, wfield, los, max_level, i, j, o, x, S);
+      else if (op == 1) render_pixel<kOpMax, kWalkStack>(T, C, field, wfield, los, max_level, i, j, o, x, S);
+      else render_pixel<kOpWMean, kWalkStack>(T, C, field, wfield, los, max_level, i, j, o, x, S);
+    } else if (lca == 2) {
+      if (op == 0) render_pixel<kOpSum, kWalkFast>(T, C, field, wfield, los, max_level, i, j, o, x, S);
+      else if (op == 1) render_pixel<kOpMax, kWalkFast>(T, C, field, wfield, los, max_level, i, j, o, x, S);
+      else render_pixel<kOpWMean, kWalkFast>(T, C, field, wfield, los, max_level, i, j, o, x, S);
+    } else {
+      if (op == 0) render_pixel<kOpSum, kWalkBase>(T, C, field, wfield, los, max_level, i, j, o, x, S);
+      else if (op == 1) render_pixel<kOpMax, kWalkBase>(T, C, field, wfield, los, max_level, i, j, o, x, S);
+      else render_pixel<kOpWMean, kWalkBase>(T, C, field, wfield, los, max_level, i, j, o, x, S);
+    }
     if (out) out[r] = o;
     if (aux) aux[r] = x;
     if (counts) counts[r] = trace_pixel(T, C, max_level, i, j, nullptr, 0);

@@ -8,7 +8,8 @@ import pytest
 import paper_1210_8014_amd as amr
 
 # (packet width, waves per block, XCD remap) per variant, in library order
-VARIANTS = [(8, 4, True), (8, 2, True), (8, 1, True), (8, 8, True), (16, 4, True), (32, 4, True), (8, 4, False)]
+VARIANTS = [(8, 1, False), (8, 2, False), (8, 4, False), (16, 4, False), (32, 2, False), (8, 1, False), (8, 4, False),
+            (8, 1, False), (8, 4, True)]
 
 
 def xcd_remap(b, nb):
@@ -41,7 +42,7 @@ def test_variant_table_matches_library():
     assert len(names) == len(VARIANTS)
     for (pw, wpb, remap), n in zip(VARIANTS, names):
         assert n.startswith(f"p{pw}x{64 // pw}_w{wpb}_")
-        assert n.endswith("xcd") == remap
+        assert n.endswith("xcdband") == remap
 
 
 @pytest.mark.parametrize("W,H", [(1, 1), (37, 23), (64, 64), (256, 256), (130, 9), (9, 130), (517, 211)])
