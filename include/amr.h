@@ -192,6 +192,51 @@ amr_status amr_render(const amr_tree* t, const amr_camera* cam, amr_op op, const
 int32_t amr_variant_count(void);
 const char* amr_variant_name(int32_t v);
 
+/* ---------------------------------------------------------------- batch */
+
+/* Many images in one launch (the paper renders independent images in
+ * parallel with dynamic master/worker load balancing, Sec. 3.1-3.2): image k
+ * renders tree trees[pairs[2k]] through camera cams[pairs[2k+1]] with op and
+ * opts into outs[k] (device fp32, H x W of that camera; auxs[k] the WMEAN
+ * weight plane or auxs == NULL).  The plan copies the trees' and cameras'
+ * descriptions to the device, orders images largest first and owns a
+ * hipGraph (queue reset + persistent kernel over a global atomic queue of
+ * 64-ray packets) captured on first use.  Output pointers are fixed at
+ * creation.  Every image is bit-identical to amr_render of the same image.
+ * The trees must outlive the plan; amr_render_batch returns AMR_ESTALE if one
+ * was freed.  Creation allocates device memory (AMR_ENOMEM); rendering does
+ * not.  Concurrent launches of one plan race on its queue counter. */
+typedef struct amr_batch amr_batch;
+amr_status amr_batch_create(const amr_tree* const* trees, int32_t ntrees, const amr_camera* cams, int32_t ncams,
+                            const int32_t* pairs, int32_t npairs, amr_op op, const amr_render_opts* opts,
+                            float* const* outs, float* const* auxs, amr_batch** plan);
+amr_status amr_render_batch(amr_batch* plan, amr_stream s);
+void amr_batch_free(amr_batch* plan);
+
+/* Persistent-kernel configurations (packet shape, descent mode, waves per
+ * CU, packets per queue pop), the current one, and explicit selection. */
+int32_t amr_batch_config_count(void);
+const char* amr_batch_config_name(int32_t c);
+int32_t amr_batch_config(const amr_batch* plan);
+amr_status amr_batch_set_config(amr_batch* plan, int32_t c);
+
+/* Autotuner for a plan: runs every configuration reps times (after one
+ * warm-up, synchronously on the plan's own stream), keeps the fastest and
+ * returns it in *best; times_ms (NULL or amr_batch_config_count() floats)
+ * receives the best time of each.  The outputs are overwritten. */
+amr_status amr_batch_tune(amr_batch* plan, int32_t reps, int32_t* best, float* times_ms);
+
+/* Autotuner for single images: times every amr_render variant on this
+ * (tree, camera, op) on stream s (synchronising it), stores the fastest as
+ * the tree's default for op (used when opts.variant is -1) and returns it;
+ * times_ms (NULL or amr_variant_count() floats) receives each best time.
+ * out/aux are overwritten. */
+amr_status amr_tune(amr_tree* t, const amr_camera* cam, amr_op op, const amr_render_opts* opts, float* out,
+                    float* aux, amr_stream s, int32_t reps, int32_t* best, float* times_ms);
+/* Set the tree's default variant for op directly (-1: variant 0), e.g. from
+ * a saved tuning cache. */
+amr_status amr_set_default_variant(amr_tree* t, amr_op op, int32_t v);
+
 /* ---------------------------------------------------------------- debug */
 
 /* Segments (cells met) per ray for every pixel: counts (device int32 H x W,

@@ -192,3 +192,112 @@ def trace_rays(tree: Tree, cam: Camera, ray_ids, offsets, cells, stream=None):
 def variants():
     L = lib()
     return [L.amr_variant_name(v).decode() for v in range(L.amr_variant_count())]
+
+
+# ----------------------------------------------------------------- batch
+
+class Batch:
+    """Persistent, graph-captured render of many (tree, camera) images
+    (amr_batch_create / amr_render_batch).  outs[k] (and auxs[k]) are device
+    tensors fixed at creation."""
+
+    def __init__(self, trees, cams, pairs, op, outs, auxs=None, field=0, weight=0, los=False):
+        L = lib()
+        self._trees = list(trees)  # keep the Python handles alive
+        nt, nc, n = len(trees), len(cams), len(pairs)
+        th = (ctypes.c_void_p * nt)(*[t.handle.value for t in trees])
+        ca = (Camera * nc)(*cams)
+        pr = (ctypes.c_int32 * (2 * n))(*[int(v) for p in pairs for v in p])
+        oa = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+        xa = (ctypes.c_void_p * n)(*[x.data_ptr() for x in auxs]) if auxs is not None else None
+        o = RenderOpts(field, weight, int(bool(los)), -1)
+        h = ctypes.c_void_p()
+        _check(L.amr_batch_create(th, nt, ca, nc, pr, n, op, ctypes.byref(o), oa, xa, ctypes.byref(h)))
+        self._h = h
+        self.outs, self.auxs = outs, auxs
+
+    def run(self, stream=None):
+        _check(lib().amr_render_batch(self._h, _stream(stream)))
+
+    def tune(self, reps: int = 2):
+        L = lib()
+        n = L.amr_batch_config_count()
+        times = (ctypes.c_float * n)()
+        best = ctypes.c_int32()
+        _check(L.amr_batch_tune(self._h, reps, ctypes.byref(best), times))
+        return int(best.value), {L.amr_batch_config_name(c).decode(): float(times[c]) for c in range(n)}
+
+    def set_config(self, c: int):
+        _check(lib().amr_batch_set_config(self._h, c))
+
+    @property
+    def config(self) -> int:
+        return int(lib().amr_batch_config(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().amr_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_configs():
+    L = lib()
+    return [L.amr_batch_config_name(c).decode() for c in range(L.amr_batch_config_count())]
+
+
+# ----------------------------------------------------------------- tuning
+
+def tune(tree: Tree, cam: Camera, op: int, out, aux=None, field: int = 0, weight: int = 0, los: bool = False,
+         reps: int = 2, stream=None, cache: Optional[str] = None):
+    """Time every kernel variant on this image, make the fastest the tree's
+    default for ``op`` and return (best, {variant: ms}).  With ``cache`` (a
+    JSON path, default $AMR_TUNE_CACHE) the choice is stored under a key of
+    the tree shape, image size and op, and reused by :func:`apply_tuning`."""
+    L = lib()
+    n = L.amr_variant_count()
+    times = (ctypes.c_float * n)()
+    best = ctypes.c_int32()
+    o = RenderOpts(field, weight, int(bool(los)), -1)
+    _check(L.amr_tune(tree.handle, ctypes.byref(cam), op, ctypes.byref(o), _ptr(out), _ptr(aux), _stream(stream),
+                      reps, ctypes.byref(best), times))
+    res = {L.amr_variant_name(v).decode(): float(times[v]) for v in range(n)}
+    path = cache or os.environ.get("AMR_TUNE_CACHE")
+    if path:
+        import json
+
+        data = {}
+        if os.path.exists(path):
+            with open(path) as f:
+                data = json.load(f)
+        data[_tune_key(tree, cam, op)] = L.amr_variant_name(best.value).decode()
+        with open(path, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+    return int(best.value), res
+
+
+def _tune_key(tree: Tree, cam: Camera, op: int) -> str:
+    i = tree.info
+    return f"gfx950/cells{i.ncells}/l{i.levelmin}-{i.lmax}/cam{cam.kind}/{cam.W}x{cam.H}/L{cam.max_level}/op{op}"
+
+
+def apply_tuning(tree: Tree, cam: Camera, op: int, cache: Optional[str] = None) -> int:
+    """Set the tree's default variant for ``op`` from the tuning cache;
+    returns the variant (or -1 if the cache has no entry)."""
+    import json
+
+    path = cache or os.environ.get("AMR_TUNE_CACHE")
+    if not path or not os.path.exists(path):
+        return -1
+    with open(path) as f:
+        name = json.load(f).get(_tune_key(tree, cam, op))
+    if name is None or name not in variants():
+        return -1
+    v = variants().index(name)
+    _check(lib().amr_set_default_variant(tree.handle, op, v))
+    return v

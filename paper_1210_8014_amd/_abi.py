@@ -61,6 +61,19 @@ SIGNATURES = {
     "amr_count_segments": (_i32, [_vp, ctypes.POINTER(Camera), _vp, _vp, _vp]),
     "amr_trace_rays": (_i32, [_vp, ctypes.POINTER(Camera), _vp, _i64, _vp, _vp, _vp]),
     "amr_count_rays": (_i32, [_vp, ctypes.POINTER(Camera), _vp, _i64, _vp, _vp]),
+    "amr_batch_create": (_i32, [ctypes.POINTER(_vp), _i32, ctypes.POINTER(Camera), _i32, ctypes.POINTER(_i32), _i32,
+                                _i32, ctypes.POINTER(RenderOpts), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                ctypes.POINTER(_vp)]),
+    "amr_render_batch": (_i32, [_vp, _vp]),
+    "amr_batch_free": (None, [_vp]),
+    "amr_batch_config_count": (_i32, []),
+    "amr_batch_config_name": (ctypes.c_char_p, [_i32]),
+    "amr_batch_config": (_i32, [_vp]),
+    "amr_batch_set_config": (_i32, [_vp, _i32]),
+    "amr_batch_tune": (_i32, [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_float)]),
+    "amr_tune": (_i32, [_vp, ctypes.POINTER(Camera), _i32, ctypes.POINTER(RenderOpts), _vp, _vp, _vp, _i32,
+                        ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_float)]),
+    "amr_set_default_variant": (_i32, [_vp, _i32, _i32]),
 }
 
 

@@ -20,6 +20,7 @@ struct amr_tree {
   std::vector<float> h_val;
   std::vector<uint8_t> h_maxdepth;
   uint64_t serial = 0;      // unique id (batches detect freed trees)
+  int32_t tuned_variant[3] = {-1, -1, -1};  // default kernel variant per op (-1: variant 0)
 };
 
 namespace amr {
@@ -46,6 +47,10 @@ int launch_rays(const TreeView& t, const CameraView& c, const int64_t* ray_ids, 
 int variant_count();
 const char* variant_name(int v);
 int variant_packet_width(int v);
+
+// Live-tree registry (batch.hip): batches refuse to run on freed trees.
+void register_tree(uint64_t serial);
+void unregister_tree(uint64_t serial);
 
 // HIP runtime wrappers (render.hip) so the host builder needs no HIP headers.
 int dev_malloc(void** p, size_t bytes);

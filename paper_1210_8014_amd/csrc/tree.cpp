@@ -362,6 +362,7 @@ amr_status amr_build_linear_octree(const amr_leaves* in, const amr_build_opts* o
   V.lmax = lmax;
   for (int l = 0; l <= kMaxLevel + 1; ++l) V.off[l] = (int32_t)off[l];
   T->serial = g_serial.fetch_add(1);
+  register_tree(T->serial);
   if (host_only) {
     T->h_child.swap(child);
     T->h_val.swap(v32);
@@ -394,6 +395,7 @@ amr_status amr_build_linear_octree(const amr_leaves* in, const amr_build_opts* o
 
 void amr_tree_free(amr_tree* t) {
   if (!t) return;
+  unregister_tree(t->serial);
   if (t->d_child) dev_free(t->d_child);
   if (t->d_val) dev_free(t->d_val);
   if (t->d_maxdepth) dev_free(t->d_maxdepth);
@@ -521,7 +523,7 @@ amr_status amr_render(const amr_tree* t, const amr_camera* cam, amr_op op, const
   if (o.field < 0 || o.field + ((op == AMR_WMEAN && o.los_velocity) ? 2 : 0) >= nf)
     return fail(AMR_EINVAL, "field index out of range");
   if (op == AMR_WMEAN && (o.weight_field < 0 || o.weight_field >= nf)) return fail(AMR_EINVAL, "bad weight field");
-  int v = o.variant < 0 ? 0 : o.variant;
+  int v = o.variant >= 0 ? o.variant : (t->tuned_variant[op] >= 0 ? t->tuned_variant[op] : 0);
   if (v >= variant_count()) return fail(AMR_EINVAL, "bad variant");
   RenderArgs a;
   a.t = t->view;
