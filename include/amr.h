@@ -237,6 +237,94 @@ amr_status amr_tune(amr_tree* t, const amr_camera* cam, amr_op op, const amr_ren
  * a saved tuning cache. */
 amr_status amr_set_default_variant(amr_tree* t, amr_op op, int32_t v);
 
+/* ------------------------------------------------------- learned LOD */
+
+/* Learned per-tile level of detail.  Sec. 2 truncates the tree at one
+ * camera-wide level from the pixel size; here a network predicts, for each
+ * 16 x 16 pixel tile, the shallowest level L in 7..16 whose render stays
+ * within rel_tol of the full-depth render.
+ *   coarse_level  level at which the 16 probe rays per tile are walked (9)
+ *   quantile      level = first class whose cumulative probability >= q
+ *   conf_thresh   tiles whose top class probability is below it render at
+ *                 full depth (>= 1 forces full depth everywhere)
+ *   rel_tol       per-pixel tolerance of the audit (1e-3)
+ *   audit_frac    fraction of tiles re-rendered at full depth and compared;
+ *                 pixels off by more than rel_tol are overwritten and counted
+ *   audit_seed    seed of the audited-tile selection */
+typedef struct {
+  int32_t coarse_level;
+  float quantile;
+  float conf_thresh;
+  float rel_tol;
+  float audit_frac;
+  int32_t audit_seed;
+} amr_lod_config;
+
+/* Library-owned model: fp32 master parameters, bf16 copy, gradients and
+ * Adam moments on the device.  32 -> 64 -> 64 -> 64 -> 16 MLP (ReLU), the
+ * first 10 outputs are the classes of levels 7..16. */
+typedef struct amr_lod_model amr_lod_model;
+int32_t amr_lod_param_count(void);
+amr_status amr_lod_create(const amr_lod_config* cfg, uint64_t seed, amr_lod_model** out); /* He init, seeded */
+void amr_lod_free(amr_lod_model* m);
+amr_status amr_lod_save(const amr_lod_model* m, const char* path);   /* versioned binary */
+amr_status amr_lod_load(const char* path, amr_lod_model** out);      /* AMR_EMODEL on format/version */
+amr_status amr_lod_get_config(const amr_lod_model* m, amr_lod_config* cfg);
+amr_status amr_lod_set_config(amr_lod_model* m, const amr_lod_config* cfg);
+/* Host copies of the fp32 parameters / gradients (amr_lod_param_count()
+ * floats: W1[32][64], b1, W2[64][64], b2, W3[64][64], b3, W4[64][16], b4). */
+amr_status amr_lod_get_params(const amr_lod_model* m, float* host);
+amr_status amr_lod_set_params(amr_lod_model* m, const float* host);
+amr_status amr_lod_get_grads(const amr_lod_model* m, float* host);
+
+/* Tiles of a W x H image: ceil(W/16) ceil(H/16), row-major. */
+int64_t amr_lod_tiles(int32_t W, int32_t H);
+
+/* Per-tile features (device bf16 [tiles][32]) from 16 probe rays per tile
+ * walked with the tree truncated at coarse_level. */
+amr_status amr_lod_features(const amr_tree* t, const amr_camera* cam, int32_t coarse_level, uint16_t* feat,
+                            amr_stream s);
+
+/* Network forward on n feature rows: logits (device fp32 [n][16]); acts
+ * (device bf16 [3][n][64] or NULL) keeps the hidden activations for
+ * amr_lod_backward. */
+amr_status amr_lod_forward(const amr_lod_model* m, const uint16_t* feat, int64_t n, float* logits, uint16_t* acts,
+                           amr_stream s);
+
+/* Loss per sample: -log p_y + lambda * sum_{c < y} p_c over the 10 classes
+ * (labels device int8 [n]); dlogits (device fp32 [n][16]) = gradient * scale;
+ * loss_sum (device fp32, may be NULL) += sum of the losses. */
+amr_status amr_lod_loss(const float* logits, const int8_t* labels, int64_t n, float lambda, float scale,
+                        float* dlogits, float* loss_sum, amr_stream s);
+
+/* Backward: accumulates parameter gradients (fp32, in the model) from
+ * dlogits; dz is device scratch of bf16 [3][n][64] + [n][16]. */
+amr_status amr_lod_backward(amr_lod_model* m, const uint16_t* feat, const uint16_t* acts, const float* dlogits,
+                            int64_t n, uint16_t* dz, amr_stream s);
+amr_status amr_lod_zero_grads(amr_lod_model* m, amr_stream s);
+/* One Adam step (beta 0.9 / 0.999) with the accumulated gradients, which
+ * it then clears; refreshes the bf16 weights. */
+amr_status amr_lod_adam_step(amr_lod_model* m, float lr, amr_stream s);
+
+/* Training labels: imgs[0..9] are device renders (same camera, same op) at
+ * levels 7..16; the label of a tile is the first level whose render is
+ * within tol of the level-16 render at every pixel of the tile (device
+ * int8 [tiles], class = level - 7). */
+amr_status amr_lod_labels(const float* const* imgs, int32_t W, int32_t H, float tol, int8_t* labels, amr_stream s);
+
+/* Render with the learned per-tile levels (tiles at or above the camera's
+ * max_level render exactly like amr_render).  workspace: device, 256-byte
+ * aligned, at least amr_lod_workspace_bytes(W, H).  tile_levels (device int8
+ * [tiles] or NULL) receives the levels used; forced_levels (device int8
+ * [tiles] or NULL) replaces the network's choice (tests of the audit).
+ * stats: device int64[8] overwritten with tiles, fallbacks, audited tiles,
+ * overwritten pixels, sum of tile levels. */
+int64_t amr_lod_workspace_bytes(int32_t W, int32_t H);
+amr_status amr_render_lod(const amr_tree* t, const amr_camera* cam, amr_op op, const amr_lod_model* m,
+                          const amr_render_opts* opts, float* out, float* aux, int8_t* tile_levels,
+                          const int8_t* forced_levels, void* workspace, int64_t workspace_bytes, int64_t* stats,
+                          amr_stream s);
+
 /* ---------------------------------------------------------------- debug */
 
 /* Segments (cells met) per ray for every pixel: counts (device int32 H x W,

@@ -88,6 +88,8 @@ def _load():
         lib.oc_trace.argtypes = [ctypes.c_void_p, _P(Camera), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                  ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32]
         lib.oc_pixel_ray.argtypes = [_P(Camera), ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
+        lib.oc_probe_stats.argtypes = [ctypes.c_void_p, _P(Camera), ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+                                       ctypes.c_void_p, ctypes.c_int32]
         _lib = lib
     return _lib
 
@@ -198,6 +200,16 @@ class Tree:
         if rc != OK:
             raise RuntimeError(f"oracle render failed ({rc})")
         return dict(val=val, max=mx, aux=aux, absf=absf, count=cnt)
+
+    def probe_stats(self, cam: Camera, rays: np.ndarray, field: int = 0, nthreads: int = 0) -> np.ndarray:
+        """[n, 16] per-ray statistics for the learned level of detail (see
+        oc_probe_stats in oracle.c)."""
+        r = np.ascontiguousarray(rays, np.int64)
+        out = np.zeros((len(r), 16), np.float64)
+        rc = _load().oc_probe_stats(self._h, ctypes.byref(cam), field, _ptr(r), len(r), _ptr(out), int(nthreads))
+        if rc != OK:
+            raise RuntimeError(f"oracle probe stats failed ({rc})")
+        return out
 
     def trace(self, cam: Camera, rays: np.ndarray, with_t: bool = False, nthreads: int = 0):
         """Cell sequences: (offsets[n+1], cells[S,4] = level, ix, iy, iz,

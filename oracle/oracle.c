@@ -176,6 +176,7 @@ typedef struct oc_tree {
   int32_t nfields, lmax;
   double* v64; /* [nfields][cap] restricted fp64 values */
   float* v32;  /* [nfields][cap] stored fp32 values */
+  int32_t* depth; /* deepest leaf level in each node's subtree */
 } oc_tree;
 
 static int grow(oc_tree* T, int64_t need) {
@@ -194,6 +195,7 @@ void oc_tree_free(oc_tree* T) {
   free(T->nodes);
   free(T->v64);
   free(T->v32);
+  free(T->depth);
   free(T);
 }
 
@@ -316,6 +318,18 @@ int oc_tree_build(int64_t n, const int32_t* level, const int32_t* ix, const int3
     }
   }
   for (int64_t k = 0; k < (int64_t)nfields * T->n; ++k) T->v32[k] = (float)T->v64[k];
+  T->depth = (int32_t*)malloc(sizeof(int32_t) * T->n);
+  if (!T->depth) goto nomem;
+  for (int64_t i = T->n - 1; i >= 0; --i) {
+    if (T->nodes[i].state == 1) {
+      T->depth[i] = T->nodes[i].level;
+    } else {
+      int32_t m = 0;
+      for (int c = 0; c < 8; ++c)
+        if (T->depth[T->nodes[i].first_child + c] > m) m = T->depth[T->nodes[i].first_child + c];
+      T->depth[i] = m;
+    }
+  }
   free(leaf_of);
   *out = T;
   return OC_OK;
@@ -578,6 +592,63 @@ int oc_trace(const oc_tree* T, const oc_camera* C, const int64_t* ray_ids, int64
           q[0] = B.s[k].t0.num; q[1] = B.s[k].t0.den; q[2] = B.s[k].t1.num; q[3] = B.s[k].t1.den;
         }
       }
+    }
+    free(B.s);
+  }
+  return err ? OC_ENOMEM : OC_OK;
+}
+
+/*
+ * Per-ray statistics used by the learned level of detail, on the tree
+ * truncated at C->max_level: for ray r, out[16 r + ...] =
+ *   0: sum of v chord, 1: sum of chord, 2: sum of chord log10(v),
+ *   3: sum of chord log10(v)^2, 4: 1 if the ray meets the box,
+ *   5..14: chord summed by the deepest leaf level below each cell met,
+ *          clamped to 7..16 (bin = level - 7),
+ *   15: number of cells met.   (v = field `field`, fp32 stored values)
+ */
+int oc_probe_stats(const oc_tree* T, const oc_camera* C, int32_t field, const int64_t* ray_ids, int64_t nrays,
+                   double* out, int32_t nthreads) {
+  if (!T || !C || !ray_ids || !out || field < 0 || field >= T->nfields) return OC_EINVAL;
+  int err = 0;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+#pragma omp parallel
+  {
+    segbuf B = {0, 0, 0};
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t r = 0; r < nrays; ++r) {
+      int64_t o[3], d[3];
+      double* q = out + 16 * r;
+      for (int k = 0; k < 16; ++k) q[k] = 0.0;
+      if (ray_segments(T, C, ray_ids[r], &B, o, d)) {
+#pragma omp atomic write
+        err = 1;
+        continue;
+      }
+      /* the ray meets the box iff its clip against the root is non-empty */
+      segbuf R = {0, 0, 0};
+      if (visit(T, 0, o, d, 0, &R) == 0 && R.n > 0) q[4] = 1.0;
+      free(R.s);
+      double ulen = unit_length(d);
+      const float* vf = T->v32 + (int64_t)field * T->n;
+      for (int64_t k = 0; k < B.n; ++k) {
+        const double l = chord(&B.s[k], ulen);
+        const double v = (double)vf[B.s[k].node];
+        const double lg = log10(v > 1e-30 ? v : 1e-30);
+        q[0] += v * l;
+        q[1] += l;
+        q[2] += l * lg;
+        q[3] += l * lg * lg;
+        int b = T->depth[B.s[k].node] - 7;
+        if (b < 0) b = 0;
+        if (b > 9) b = 9;
+        q[5 + b] += l;
+      }
+      q[15] = (double)B.n;
     }
     free(B.s);
   }
