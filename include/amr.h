@@ -241,7 +241,7 @@ amr_status amr_set_default_variant(amr_tree* t, amr_op op, int32_t v);
 
 /* Learned per-tile level of detail.  Sec. 2 truncates the tree at one
  * camera-wide level from the pixel size; here a network predicts, for each
- * 16 x 16 pixel tile, the shallowest level L in 7..16 whose render stays
+ * 16 x 16 pixel tile, the shallowest level L in 1..16 whose render stays
  * within rel_tol of the full-depth render.
  *   coarse_level  level at which the 16 probe rays per tile are walked (9)
  *   quantile      level = first class whose cumulative probability >= q
@@ -261,8 +261,8 @@ typedef struct {
 } amr_lod_config;
 
 /* Library-owned model: fp32 master parameters, bf16 copy, gradients and
- * Adam moments on the device.  32 -> 64 -> 64 -> 64 -> 16 MLP (ReLU), the
- * first 10 outputs are the classes of levels 7..16. */
+ * Adam moments on the device.  32 -> 64 -> 64 -> 64 -> 16 MLP (ReLU); the
+ * 16 outputs are the classes of levels 1..16. */
 typedef struct amr_lod_model amr_lod_model;
 int32_t amr_lod_param_count(void);
 amr_status amr_lod_create(const amr_lod_config* cfg, uint64_t seed, amr_lod_model** out); /* He init, seeded */
@@ -291,7 +291,7 @@ amr_status amr_lod_features(const amr_tree* t, const amr_camera* cam, int32_t co
 amr_status amr_lod_forward(const amr_lod_model* m, const uint16_t* feat, int64_t n, float* logits, uint16_t* acts,
                            amr_stream s);
 
-/* Loss per sample: -log p_y + lambda * sum_{c < y} p_c over the 10 classes
+/* Loss per sample: -log p_y + lambda * sum_{c < y} p_c over the 16 classes
  * (labels device int8 [n]); dlogits (device fp32 [n][16]) = gradient * scale;
  * loss_sum (device fp32, may be NULL) += sum of the losses. */
 amr_status amr_lod_loss(const float* logits, const int8_t* labels, int64_t n, float lambda, float scale,
@@ -306,14 +306,15 @@ amr_status amr_lod_zero_grads(amr_lod_model* m, amr_stream s);
  * it then clears; refreshes the bf16 weights. */
 amr_status amr_lod_adam_step(amr_lod_model* m, float lr, amr_stream s);
 
-/* Training labels: imgs[0..9] are device renders (same camera, same op) at
- * levels 7..16; the label of a tile is the first level whose render is
+/* Training labels: imgs[0..15] are device renders (same camera, same op) at
+ * levels 1..16; the label of a tile is the first level whose render is
  * within tol of the level-16 render at every pixel of the tile (device
- * int8 [tiles], class = level - 7). */
+ * int8 [tiles], class = level - 1). */
 amr_status amr_lod_labels(const float* const* imgs, int32_t W, int32_t H, float tol, int8_t* labels, amr_stream s);
 
 /* Render with the learned per-tile levels (tiles at or above the camera's
- * max_level render exactly like amr_render).  workspace: device, 256-byte
+ * max_level render exactly like amr_render; audited tiles below it are
+ * rendered at both levels in the same wave).  workspace: device, 256-byte
  * aligned, at least amr_lod_workspace_bytes(W, H).  tile_levels (device int8
  * [tiles] or NULL) receives the levels used; forced_levels (device int8
  * [tiles] or NULL) replaces the network's choice (tests of the audit).

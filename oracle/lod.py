@@ -6,7 +6,8 @@ Plain NumPy, fp64 unless stated:
   * the 32 -> 64 -> 64 -> 64 -> 16 ReLU network forward and backward with
     the same bf16 roundings the GPU applies (weights, inputs, hidden
     activations, back-propagated pre-activation gradients);
-  * the loss (cross-entropy + lambda * probability of too-shallow levels)
+  * the loss over the 16 level classes 1..16 (cross-entropy + lambda *
+    probability of too-shallow levels)
     and its analytic gradient, pinned by central finite differences;
   * per-tile labels from renders at every level, and the plan (quantile
     level, confidence fallback).
@@ -19,7 +20,8 @@ import math
 
 import numpy as np
 
-IN, HID, OUT, CLS, LV0, TILE = 32, 64, 16, 10, 7, 16
+IN, HID, OUT, CLS, LV0, TILE = 32, 64, 16, 16, 1, 16
+BINS, BIN0 = 10, 7  # subtree-depth histogram of the probe features: levels 7..16
 SHAPES = [("W1", (IN, HID)), ("b1", (HID,)), ("W2", (HID, HID)), ("b2", (HID,)), ("W3", (HID, HID)),
           ("b3", (HID,)), ("W4", (HID, OUT)), ("b4", (OUT,))]
 NPARAMS = sum(int(np.prod(s)) for _, s in SHAPES)
@@ -166,7 +168,7 @@ def footprint_log2(cam, coarse_level):
 
 
 def labels_from_renders(imgs, W, H, tol):
-    """imgs: 10 images (levels 7..16) as [H*W] arrays; first level whose
+    """imgs: 16 images (levels 1..16) as [H*W] arrays; first level whose
     image is within tol of the last at every pixel of the tile."""
     tx, ty = -(-W // TILE), -(-H // TILE)
     ref = np.asarray(imgs[-1], np.float64).reshape(H, W)

@@ -8,7 +8,7 @@
 //   features  16 probe rays per tile, walked at a coarse level: column
 //             integral, the chord-weighted histogram of subtree depths,
 //             log-density statistics, pixel footprint;
-//   network   32 -> 64 -> 64 -> 64 -> 16 (10 classes = levels 7..16), ReLU,
+//   network   32 -> 64 -> 64 -> 64 -> 16 (16 classes = levels 1..16), ReLU,
 //             bf16 weights and activations, fp32 accumulation on
 //             v_mfma_f32_16x16x32_bf16;
 //   plan      softmax; level = first class whose cumulative probability
@@ -32,7 +32,9 @@
 namespace amr {
 namespace lod {
 
-constexpr int kIn = 32, kHid = 64, kOut = 16, kCls = 10, kLv0 = 7, kTile = 16;
+constexpr int kIn = 32, kHid = 64, kOut = 16, kCls = 16, kLv0 = 1, kTile = 16;
+// subtree-depth histogram of the probe features: levels 7..16
+constexpr int kBins = 10, kBin0 = 7;
 // parameter offsets (floats) in the fp32 master buffer; the bf16 weight
 // buffer uses the same offsets
 constexpr int oW1 = 0, oB1 = oW1 + kIn * kHid, oW2 = oB1 + kHid, oB2 = oW2 + kHid * kHid, oW3 = oB2 + kHid,
@@ -288,7 +290,7 @@ struct FeatVis {
   float x = 0.f;
   int depth = 0;
   float col = 0.f, len = 0.f, slg = 0.f, slg2 = 0.f;
-  float hist[kCls];
+  float hist[kBins];
   __device__ void fetch(int32_t node) {
     x = rho[node];
     depth = md[node];
@@ -299,9 +301,9 @@ struct FeatVis {
     const float lg = log10f(fmaxf(x, 1e-30f));
     slg += l * lg;
     slg2 += l * lg * lg;
-    int b = depth - kLv0;
-    b = b < 0 ? 0 : (b >= kCls ? kCls - 1 : b);
-    for (int c = 0; c < kCls; ++c) hist[c] += c == b ? l : 0.f;
+    int b = depth - kBin0;
+    b = b < 0 ? 0 : (b >= kBins ? kBins - 1 : b);
+    for (int c = 0; c < kBins; ++c) hist[c] += c == b ? l : 0.f;
   }
 };
 
@@ -320,7 +322,7 @@ __global__ __launch_bounds__(64) void k_features(TreeView T, CameraView C, int l
   FeatVis v;
   v.rho = T.val;
   v.md = T.maxdepth;
-  for (int c = 0; c < kCls; ++c) v.hist[c] = 0.f;
+  for (int c = 0; c < kBins; ++c) v.hist[c] = 0.f;
   Ray R;
   Entry E;
   int32_t nseg = 0;
@@ -334,7 +336,7 @@ __global__ __launch_bounds__(64) void k_features(TreeView T, CameraView C, int l
   s[2] = v.slg;
   s[3] = v.slg2;
   s[4] = hit ? 1.f : 0.f;
-  for (int c = 0; c < kCls; ++c) s[5 + c] = v.hist[c];
+  for (int c = 0; c < kBins; ++c) s[5 + c] = v.hist[c];
   float segs = (float)nseg;
   for (int m = 1; m < 16; m <<= 1) {
     for (int q = 0; q < 15; ++q) s[q] += __shfl_xor(s[q], m, 64);
@@ -352,7 +354,7 @@ __global__ __launch_bounds__(64) void k_features(TreeView T, CameraView C, int l
     float x = 0.f;
     if (k == 0) x = log10f(1e-12f + mean_col);
     else if (k == 1) x = log10f(1e-12f + cmax) - log10f(1e-12f + mean_col);
-    else if (k >= 2 && k < 2 + kCls) x = L > 0.f ? s[5 + (k - 2)] / L : 0.f;
+    else if (k >= 2 && k < 2 + kBins) x = L > 0.f ? s[5 + (k - 2)] / L : 0.f;
     else if (k == 12) x = mlg;
     else if (k == 13) x = vlg;
     else if (k == 14) x = foot_log2;
@@ -365,9 +367,9 @@ __global__ __launch_bounds__(64) void k_features(TreeView T, CameraView C, int l
 }
 
 // ---------------------------------------------------------------- labels
-// Per tile: the first level L (class L - 7) whose image is within tol of the
-// full-depth image at every pixel of the tile.  imgs: 10 device pointers
-// (levels 7..16); the last is the reference.
+// Per tile: the first level L (class L - 1) whose image is within tol of the
+// full-depth image at every pixel of the tile.  imgs: 16 device pointers
+// (levels 1..16); the last is the reference.
 struct ImgPtrs {
   const float* p[kCls];
 };
@@ -453,46 +455,38 @@ __global__ void k_zero_stats(unsigned long long* s) {
 }
 
 // ----------------------------------------------------- render and audit
-// 8 x 8 packets (inside one 16 x 16 tile), tree truncated at the tile's level.
+// 8 x 8 packets (inside one 16 x 16 tile), tree truncated at the tile's
+// level.  Audited tiles below full depth are also rendered at full depth in
+// the same wave; a pixel off by more than tol keeps the full-depth value
+// and is counted.
 template <int OP>
-__global__ __launch_bounds__(64) void k_render_tiles(RenderArgs A, const int8_t* __restrict__ level, int tiles_x) {
-  const int lane = threadIdx.x & 63;
-  const int packet = blockIdx.x;
-  const int ty = packet / A.packets_x, tx = packet - ty * A.packets_x;
-  const int i = tx * 8 + (lane & 7), j = ty * 8 + (lane >> 3);
-  if (ty >= A.packets_y || i >= A.c.W || j >= A.c.H) return;
-  const int L = level[(j / kTile) * tiles_x + (i / kTile)];
-  float o = 0.f, x = 0.f;
-  NoStack S;
-  render_pixel<OP, kWalkFast>(A.t, A.c, A.field, A.wfield, A.los, L, i, j, o, x, S);
-  const int64_t pix = (int64_t)j * A.c.W + i;
-  A.out[pix] = o;
-  if (OP == kOpWMean && A.aux) A.aux[pix] = x;
-}
-
-template <int OP>
-__global__ __launch_bounds__(64) void k_audit(RenderArgs A, const int8_t* __restrict__ level,
-                                              const uint8_t* __restrict__ audit, int tiles_x, float tol,
-                                              unsigned long long* stats) {
+__global__ __launch_bounds__(64) void k_render_tiles(RenderArgs A, const int8_t* __restrict__ level,
+                                                     const uint8_t* __restrict__ audit, int tiles_x, float tol,
+                                                     unsigned long long* stats) {
   const int lane = threadIdx.x & 63;
   const int packet = blockIdx.x;
   const int ty = packet / A.packets_x, tx = packet - ty * A.packets_x;
   const int i = tx * 8 + (lane & 7), j = ty * 8 + (lane >> 3);
   if (ty >= A.packets_y || i >= A.c.W || j >= A.c.H) return;
   const int t = (j / kTile) * tiles_x + (i / kTile);
-  if (!audit[t] || level[t] >= A.max_level) return;
+  const int L = level[t];
   float o = 0.f, x = 0.f;
   NoStack S;
-  render_pixel<OP, kWalkFast>(A.t, A.c, A.field, A.wfield, A.los, A.max_level, i, j, o, x, S);
-  const int64_t pix = (int64_t)j * A.c.W + i;
-  const float got = A.out[pix];
-  const float d = fabsf(got - o);
-  const bool bad = o != 0.f ? d > tol * fabsf(o) : d != 0.f;
-  if (bad) {
-    A.out[pix] = o;
-    if (OP == kOpWMean && A.aux) A.aux[pix] = x;
-    atomicAdd(&stats[3], 1ull);
+  render_pixel<OP, kWalkFast>(A.t, A.c, A.field, A.wfield, A.los, L, i, j, o, x, S);
+  if (audit[t] && L < A.max_level) {
+    float of = 0.f, xf = 0.f;
+    render_pixel<OP, kWalkFast>(A.t, A.c, A.field, A.wfield, A.los, A.max_level, i, j, of, xf, S);
+    const float d = fabsf(o - of);
+    const bool bad = of != 0.f ? d > tol * fabsf(of) : d != 0.f;
+    if (bad) {
+      o = of;
+      x = xf;
+      atomicAdd(&stats[3], 1ull);
+    }
   }
+  const int64_t pix = (int64_t)j * A.c.W + i;
+  A.out[pix] = o;
+  if (OP == kOpWMean && A.aux) A.aux[pix] = x;
 }
 
 }  // namespace lod
@@ -831,16 +825,12 @@ amr_status amr_render_lod(const amr_tree* t, const amr_camera* cam, amr_op op, c
   a.packets_x = (cam->W + 7) / 8;
   a.packets_y = (cam->H + 7) / 8;
   const unsigned np = (unsigned)(a.packets_x * a.packets_y);
-  if (op == AMR_SUM) {
-    hipLaunchKernelGGL(k_render_tiles<kOpSum>, dim3(np), dim3(64), 0, hs, a, lev, tx);
-    hipLaunchKernelGGL(k_audit<kOpSum>, dim3(np), dim3(64), 0, hs, a, lev, aud, tx, c.rel_tol, st);
-  } else if (op == AMR_MAX) {
-    hipLaunchKernelGGL(k_render_tiles<kOpMax>, dim3(np), dim3(64), 0, hs, a, lev, tx);
-    hipLaunchKernelGGL(k_audit<kOpMax>, dim3(np), dim3(64), 0, hs, a, lev, aud, tx, c.rel_tol, st);
-  } else {
-    hipLaunchKernelGGL(k_render_tiles<kOpWMean>, dim3(np), dim3(64), 0, hs, a, lev, tx);
-    hipLaunchKernelGGL(k_audit<kOpWMean>, dim3(np), dim3(64), 0, hs, a, lev, aud, tx, c.rel_tol, st);
-  }
+  if (op == AMR_SUM)
+    hipLaunchKernelGGL(k_render_tiles<kOpSum>, dim3(np), dim3(64), 0, hs, a, lev, aud, tx, c.rel_tol, st);
+  else if (op == AMR_MAX)
+    hipLaunchKernelGGL(k_render_tiles<kOpMax>, dim3(np), dim3(64), 0, hs, a, lev, aud, tx, c.rel_tol, st);
+  else
+    hipLaunchKernelGGL(k_render_tiles<kOpWMean>, dim3(np), dim3(64), 0, hs, a, lev, aud, tx, c.rel_tol, st);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? AMR_OK : fail(AMR_EHIP, hipGetErrorString(e));
 }

@@ -15,7 +15,7 @@ from . import SUM, Camera, RenderOpts, Tree, _check, _ptr, _stream, lib, render,
 
 _vp = ctypes.c_void_p
 _i32, _i64, _f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
-NCLS, LV0, TILE, NIN, NHID, NOUT = 10, 7, 16, 32, 64, 16
+NCLS, LV0, TILE, NIN, NHID, NOUT = 16, 1, 16, 32, 64, 16
 MODEL_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "lod_model.bin")
 
 

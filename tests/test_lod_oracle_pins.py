@@ -29,13 +29,13 @@ def test_bf16_rounding_cases(L):
 
 def test_loss_closed_forms(L):
     z = np.zeros((3, 16))
-    y = np.array([0, 4, 9])
+    y = np.array([0, 4, 15])
     loss, g = L.loss_and_grad(z, y, 0.5)
-    assert np.allclose(loss, math.log(10) + 0.5 * y / 10.0)
-    assert np.allclose(g[:, 10:], 0.0)
+    u = 1.0 / 16
+    assert np.allclose(loss, math.log(16) + 0.5 * y * u)
     for k, yy in enumerate(y):
-        want = np.array([0.1 - (j == yy) + 0.5 * 0.1 * ((j < yy) - 0.1 * yy) for j in range(10)])
-        assert np.allclose(g[k, :10], want)
+        want = np.array([u - (j == yy) + 0.5 * u * ((j < yy) - u * yy) for j in range(16)])
+        assert np.allclose(g[k], want)
     p = L.softmax10(np.random.default_rng(0).normal(size=(5, 16)))
     assert np.allclose(p.sum(axis=1), 1.0)
 
@@ -43,7 +43,7 @@ def test_loss_closed_forms(L):
 def test_loss_gradient_matches_finite_differences(L):
     rng = np.random.default_rng(1)
     z = rng.normal(size=(6, 16)) * 2
-    y = rng.integers(0, 10, 6)
+    y = rng.integers(0, 16, 6)
     for lam in (0.0, 2.0):
         _, g = L.loss_and_grad(z, y, lam)
         num = np.zeros_like(z)
@@ -61,7 +61,7 @@ def test_parameter_gradients_match_finite_differences(L):
     rng = np.random.default_rng(2)
     params = rng.normal(size=L.NPARAMS) * 0.3
     X = rng.normal(size=(7, 32))
-    y = rng.integers(0, 10, 7)
+    y = rng.integers(0, 16, 7)
     lam = 1.5
     logits, acts = L.forward(params, X, emulate=False)
     _, dl = L.loss_and_grad(logits, y, lam)
@@ -77,31 +77,31 @@ def test_parameter_gradients_match_finite_differences(L):
 
 
 def test_labels_hand_made(L):
-    W = H = 32  # 4 tiles
+    W = H = 32  # 4 tiles; 16 renders (levels 1..16), the last is the reference
     ref = np.ones((H, W))
-    imgs = [ref.copy() * 2 for _ in range(9)] + [ref]
+    imgs = [ref.copy() * 2 for _ in range(15)] + [ref]
     # tile 0: exact from class 3; tile 1: within tol from class 5; tile 2: never; tile 3: exact everywhere
-    for c in range(3, 9):
+    for c in range(3, 15):
         imgs[c][0:16, 0:16] = 1.0
-    for c in range(5, 9):
+    for c in range(5, 15):
         imgs[c][0:16, 16:32] = 1.0 + 0.9e-3
-    for c in range(9):
+    for c in range(15):
         imgs[c][16:32, 16:32] = 1.0
     imgs[4][0:16, 16:32] = 1.0 + 1.1e-3  # class 4 just outside the tolerance
     lab = L.labels_from_renders([x.ravel() for x in imgs], W, H, 1e-3)
-    assert lab.tolist() == [3, 5, 9, 0]
+    assert lab.tolist() == [3, 5, 15, 0]
 
 
 def test_plan_quantile_and_fallback(L):
     z = np.full((3, 16), -20.0)
-    z[0, 2] = 10.0                     # confident class 2 -> level 9
-    z[1, :10] = 0.0                    # uniform -> low confidence -> full
+    z[0, 2] = 10.0                     # confident class 2 -> level 3
+    z[1, :] = 0.0                      # uniform -> low confidence -> full
     z[2, 4] = 3.0
-    z[2, 6] = 3.0                      # two equal peaks: cdf reaches 0.99 at class 6
+    z[2, 6] = 3.0                      # two equal peaks: cdf reaches 0.99 at class 6 -> level 7
     lev, fb = L.plan(z, 0.99, 0.4, 16)
-    assert lev.tolist() == [9, 16, 13] and fb.tolist() == [False, True, False]
+    assert lev.tolist() == [3, 16, 7] and fb.tolist() == [False, True, False]
     lev2, fb2 = L.plan(z, 0.99, 0.6, 16)
-    assert lev2.tolist() == [9, 16, 16] and fb2.tolist() == [False, True, True]
+    assert lev2.tolist() == [3, 16, 16] and fb2.tolist() == [False, True, True]
     lev3, fb3 = L.plan(z, 0.99, 1.0, 16)
     assert np.all(lev3 == 16) and np.all(fb3)
 
