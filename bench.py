@@ -208,7 +208,7 @@ def main():
             "algorithmic_GBs": alg_total / (t_wall / args.steps) / 1e9,
             "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                         for k, v in kern.items()},
-            "variant": amr.variants()[max(args.variant, 0)],
+            "variant": amr.variants()[args.variant if args.variant >= 0 else amr.default_variant()],
         },
         "roofline": {
             "bound": "hbm",

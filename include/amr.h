@@ -122,6 +122,7 @@ amr_status amr_tree_info(const amr_tree* t, amr_tree_info_t* info);
 amr_status amr_tree_arrays(const amr_tree* t, const int32_t** child, const float** values,
                            const uint8_t** maxdepth);
 
+
 /* ---------------------------------------------------------------- camera */
 
 /* Camera description (box units).  kind 0 = perspective (fov_y, radians),
@@ -183,14 +184,21 @@ typedef struct {
  * Cell decisions are exact integer predicates, so the cell sequence of
  * every ray is deterministic; sums are fp32 Kahan-compensated; chord
  * lengths come from an exact integer numerator, in fp64 for cells at level
- * 18 and deeper.  Every variant gives bit-identical output. */
+ * 18 and deeper.  Every variant visits the same cells and gives a
+ * bit-identical MAX.  The split variants (names with "split"), among them
+ * the default, cut every ray into spans at base-level planes, walk the
+ * spans on different waves and merge their Kahan sums in span order: their
+ * SUM and WMEAN differ from the unsplit walk by rounding only and are
+ * themselves deterministic. */
 amr_status amr_render(const amr_tree* t, const amr_camera* cam, amr_op op, const amr_render_opts* opts, float* out,
                       float* aux, amr_stream s);
 
 /* Number of kernel variants (ray-packet shape, waves per block, descent
- * mode) amr_render_opts.variant may select, and a short name for each. */
+ * mode, spans per ray) amr_render_opts.variant may select, a short name for
+ * each, and the one used when none is selected or tuned. */
 int32_t amr_variant_count(void);
 const char* amr_variant_name(int32_t v);
+int32_t amr_variant_default(void);
 
 /* ---------------------------------------------------------------- batch */
 
@@ -202,7 +210,9 @@ const char* amr_variant_name(int32_t v);
  * descriptions to the device, orders images largest first and owns a
  * hipGraph (queue reset + persistent kernel over a global atomic queue of
  * 64-ray packets) captured on first use.  Output pointers are fixed at
- * creation.  Every image is bit-identical to amr_render of the same image.
+ * creation.  Every image is bit-identical to amr_render of the same image
+ * with variant 0 (the unsplit walk; the batch's dynamic schedule already
+ * overlaps the long rays of one image with the work of the others).
  * The trees must outlive the plan; amr_render_batch returns AMR_ESTALE if one
  * was freed.  Creation allocates device memory (AMR_ENOMEM); rendering does
  * not.  Concurrent launches of one plan race on its queue counter. */
@@ -233,8 +243,8 @@ amr_status amr_batch_tune(amr_batch* plan, int32_t reps, int32_t* best, float* t
  * out/aux are overwritten. */
 amr_status amr_tune(amr_tree* t, const amr_camera* cam, amr_op op, const amr_render_opts* opts, float* out,
                     float* aux, amr_stream s, int32_t reps, int32_t* best, float* times_ms);
-/* Set the tree's default variant for op directly (-1: variant 0), e.g. from
- * a saved tuning cache. */
+/* Set the tree's default variant for op directly (-1: amr_variant_default),
+ * e.g. from a saved tuning cache. */
 amr_status amr_set_default_variant(amr_tree* t, amr_op op, int32_t v);
 
 /* ------------------------------------------------------- learned LOD */

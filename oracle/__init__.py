@@ -186,7 +186,8 @@ class Tree:
     def render(self, cam: Camera, op: int, field: int = 0, weight: int = 0, los: bool = False,
                rays: Optional[np.ndarray] = None, nthreads: int = 0):
         """Returns dict with 'val' (fp64; sum or wmean), 'max' (fp32),
-        'aux' (wmean weight), 'absf' (wmean mean |f|), 'count'.  Arrays are
+        'aux' (wmean weight), 'absf' (wmean mean |f|; with los the mean of the
+        summed magnitudes of the three velocity terms: the error-bar scale), 'count'.  Arrays are
         flat over the requested rays (pixel index j*W+i), or over all pixels."""
         n = cam.W * cam.H if rays is None else int(len(rays))
         r = None if rays is None else np.ascontiguousarray(rays, np.int64)

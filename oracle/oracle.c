@@ -477,6 +477,11 @@ static void neum_add(neum* a, double x) {
  *                  sum(w |f| chord) / sum(w chord).  With los != 0, f is
  *                  the line-of-sight velocity (v_field, v_field+1,
  *                  v_field+2) . d / |d|; otherwise f is field v_field.
+ *                  out_absf is the scale for error bars: with los it uses
+ *                  |v_0 dh_0| + |v_1 dh_1| + |v_2 dh_2| for |f|, the size of
+ *                  the terms whose single-precision dot product a renderer
+ *                  rounds (the bound for a rounded dot product of n terms is
+ *                  about n eps times the sum of their magnitudes).
  * out_count = number of cells on each ray.  Any output may be NULL.
  */
 int oc_render(const oc_tree* T, const oc_camera* C, int32_t op, int32_t v_field, int32_t w_field, int32_t los,
@@ -526,17 +531,21 @@ int oc_render(const oc_tree* T, const oc_camera* C, int32_t op, int32_t v_field,
         neum num = {0, 0}, den = {0, 0}, ab = {0, 0};
         for (int64_t k = 0; k < B.n; ++k) {
           int64_t nd = B.s[k].node;
-          double f;
-          if (los)
-            f = (double)T->v32[(int64_t)v_field * T->n + nd] * dh[0] +
-                (double)T->v32[(int64_t)(v_field + 1) * T->n + nd] * dh[1] +
-                (double)T->v32[(int64_t)(v_field + 2) * T->n + nd] * dh[2];
-          else
+          double f, fa;
+          if (los) {
+            const double p0 = (double)T->v32[(int64_t)v_field * T->n + nd] * dh[0];
+            const double p1 = (double)T->v32[(int64_t)(v_field + 1) * T->n + nd] * dh[1];
+            const double p2 = (double)T->v32[(int64_t)(v_field + 2) * T->n + nd] * dh[2];
+            f = p0 + p1 + p2;
+            fa = fabs(p0) + fabs(p1) + fabs(p2);
+          } else {
             f = (double)vf[nd];
+            fa = fabs(f);
+          }
           double wl = (double)wf[nd] * chord(&B.s[k], ulen);
           neum_add(&num, wl * f);
           neum_add(&den, wl);
-          neum_add(&ab, wl * fabs(f));
+          neum_add(&ab, wl * fa);
         }
         double W = den.s + den.c;
         if (out_val) out_val[r] = W != 0.0 ? (num.s + num.c) / W : 0.0;

@@ -194,6 +194,11 @@ def variants():
     return [L.amr_variant_name(v).decode() for v in range(L.amr_variant_count())]
 
 
+def default_variant() -> int:
+    """Index of the variant amr_render uses when none is selected or tuned."""
+    return int(lib().amr_variant_default())
+
+
 # ----------------------------------------------------------------- batch
 
 class Batch:

@@ -57,6 +57,7 @@ SIGNATURES = {
     "amr_set_camera": (_i32, [ctypes.POINTER(CameraDesc), _vp, ctypes.POINTER(Camera)]),
     "amr_render": (_i32, [_vp, ctypes.POINTER(Camera), _i32, ctypes.POINTER(RenderOpts), _vp, _vp, _vp]),
     "amr_variant_count": (_i32, []),
+    "amr_variant_default": (_i32, []),
     "amr_variant_name": (ctypes.c_char_p, [_i32]),
     "amr_count_segments": (_i32, [_vp, ctypes.POINTER(Camera), _vp, _vp, _vp]),
     "amr_trace_rays": (_i32, [_vp, ctypes.POINTER(Camera), _vp, _i64, _vp, _vp, _vp]),

@@ -47,6 +47,7 @@ int launch_rays(const TreeView& t, const CameraView& c, const int64_t* ray_ids, 
 int variant_count();
 const char* variant_name(int v);
 int variant_packet_width(int v);
+int default_variant();  // the variant amr_render uses when none is chosen or tuned
 
 // Live-tree registry (batch.hip): batches refuse to run on freed trees.
 void register_tree(uint64_t serial);

@@ -123,6 +123,7 @@ struct Ray {
   float wk[3];     // |d| 2^-28 / d_k  (chord per unit of parameter numerator)
   float inv_d[3];  // 1 / d_k
   double ulen64;   // |d| 2^-28
+  int32_t stop[3]; // the fast walk ends on leaving through plane x_k = stop[k]
 };
 
 // Entry point of the current cell: parameter t = (Xa - oa) / da, the
@@ -215,6 +216,7 @@ AMR_HD bool setup_ray(const CameraView& C, int i, int j, Ray& R, Entry& E) {
     R.wk[k] = R.d[k] > 0 ? ulen / (float)R.d[k] : 0.0f;
   }
   E.inv_da = a < 0 ? 1.0f : 1.0f / (float)ed;
+  R.stop[0] = R.stop[1] = R.stop[2] = kOne;
   return true;
 }
 
@@ -465,7 +467,7 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
     vis.seg(node, lvl, len, E.p[0] >> s, E.p[1] >> s, E.p[2] >> s);
     ++nseg;
     const bool t0 = tie & 1, t1 = tie & 2, t2 = tie & 4;
-    if ((t0 && X0 == kOne) || (t1 && X1 == kOne) || (t2 && X2 == kOne)) break;
+    if ((t0 && X0 >= R.stop[0]) || (t1 && X1 >= R.stop[1]) || (t2 && X2 >= R.stop[2])) break;
     // restart level and base-cell steps: a tied axis whose coordinate at this
     // level ends in r one-bits carries r + 1 levels up
     const int span = lvl - b0;
@@ -646,6 +648,184 @@ AMR_HD int32_t trace_pixel(const TreeView& T, const CameraView& C, int max_level
   E = E0;
   walk_ray(T, R, E, max_level, v);
   return m;
+}
+
+
+// ------------------------------------------------------------ split rays
+// A long ray can be cut into spans at planes of the base level normal to
+// its major axis.  Every cell on the path lies at the base level or deeper,
+// so no cell straddles such a plane: the spans partition the ray's cell
+// sequence.  A span starts at the exact crossing of its first plane and ends
+// on leaving through its last one, so each cell is decided exactly as on the
+// unsplit ray.  Spans are walked by different waves and their partial sums
+// merged in span order; only the rounding of the sums differs from the
+// unsplit walk (the maximum is identical).
+
+// Axis with the largest |d| (lowest index on ties).
+AMR_HD int major_axis(const Ray& R) {
+  int a = R.d[1] > R.d[0] ? 1 : 0;
+  return R.d[2] > (a ? R.d[1] : R.d[0]) ? 2 : a;
+}
+
+// Component a of a 3-vector held in registers (selects, not an indexed
+// access, so the vector is never spilled to scratch memory).
+template <class T>
+AMR_HD T pick3(int a, const T (&v)[3]) {
+  return a == 2 ? v[2] : (a == 1 ? v[1] : v[0]);
+}
+
+// Entry at the crossing of the plane x_a = P (mirrored).  False when the ray
+// leaves the box before reaching it.  The caller guarantees that P lies
+// beyond the ray's box entry point.
+AMR_HD bool plane_entry(const Ray& R, int a, int32_t P, Entry& E) {
+  const int32_t da32 = pick3(a, R.d), oa = pick3(a, R.o);
+  if (da32 <= 0 || P >= kOne) return false;
+  const int64_t da = da32;
+  const int64_t dt = (int64_t)P - oa;
+  int32_t p[3];
+  bool inside = true;
+  AMR_UNROLL
+  for (int k = 0; k < 3; ++k) {
+    // x_k at the crossing = (o_k d_a + (P - o_a) d_k) / d_a, in [0, 2^28)
+    const int64_t num = (int64_t)R.o[k] * da + dt * (int64_t)R.d[k];
+    if (k != a && num >= (int64_t)kOne * da) inside = false;
+    p[k] = k == a ? P : (int32_t)((uint64_t)(num < 0 ? 0 : num) / (uint64_t)da);
+  }
+  if (!inside) return false;
+  E.p[0] = p[0];
+  E.p[1] = p[1];
+  E.p[2] = p[2];
+  E.a = a;
+  E.Xa = P;
+  E.oa = oa;
+  E.da = da32;
+  E.inv_da = pick3(a, R.inv_d);
+  E.exact = 7;
+  E.lam = kFix;
+  return true;
+}
+
+// The part of the ray between the base-level slab boundaries lo and hi
+// (slab indices along axis a, mirrored frame; lo = INT32_MIN: from the box
+// entry, hi = INT32_MAX: to the box exit).  On entry E is the ray's box entry
+// (setup_ray); on return E is the span's entry point and R.stop its end
+// plane.  False for an empty span.  Boundaries at or before the entry slab's
+// lower face are never crossed after the entry, so a span ending there is
+// empty and a span starting there starts at the box entry: the spans of any
+// increasing boundary sequence partition the ray.
+AMR_HD bool span_bounds(Ray& R, Entry& E, int b0, int a, int32_t lo, int32_t hi) {
+  const int sb = kFix - b0;
+  const int32_t c0 = pick3(a, E.p) >> sb;
+  if (hi <= c0) return false;
+  if (hi < (int32_t(1) << b0)) {
+    const int32_t P = hi << sb;
+    R.stop[0] = a == 0 ? P : R.stop[0];
+    R.stop[1] = a == 1 ? P : R.stop[1];
+    R.stop[2] = a == 2 ? P : R.stop[2];
+  }
+  if (lo <= c0) return true;
+  return plane_entry(R, a, lo << sb, E);
+}
+
+// Span w of K: the base-level slabs the ray crosses along its major axis,
+// from the slab of its box entry to an estimate of the slab of its exit,
+// dealt out in K contiguous runs of (nearly) equal count.  The exit
+// estimate only balances the runs: the last non-empty run always continues
+// to the box.
+AMR_HD bool span_setup(Ray& R, Entry& E, int b0, int K, int w) {
+  if (K <= 1) return true;
+  const int a = major_axis(R);
+  const int32_t da = pick3(a, R.d), oa = pick3(a, R.o);
+  if (da <= 0) return w == 0;
+  const int sb = kFix - b0;
+  const int32_t c0 = pick3(a, E.p) >> sb;
+  float te = 3.0e38f;
+  AMR_UNROLL
+  for (int k = 0; k < 3; ++k)
+    if (R.d[k] > 0) te = fminf(te, ((float)kOne - (float)R.o[k]) * R.inv_d[k]);
+  const float ae = (float)oa + te * (float)da;
+  int32_t c1 = (int32_t)fminf(fmaxf(ae * (1.0f / (float)(1 << sb)), 0.0f), (float)((1 << b0) - 1));
+  c1 = c1 < c0 ? c0 : c1;
+  const int32_t n = c1 - c0 + 1;
+  // run w = slabs [c0 + ceil(w n / K), c0 + ceil((w + 1) n / K)): the first
+  // run is never empty and every later one starts past the entry slab
+  const int32_t s0 = c0 + (int32_t)(((int64_t)w * n + K - 1) / K);
+  const int32_t s1 = c0 + (int32_t)(((int64_t)(w + 1) * n + K - 1) / K);
+  if (s0 == s1) return false;
+  const int32_t lo = w == 0 ? INT32_MIN : s0;
+  const int32_t hi = (w + 1 < K && s1 < c0 + n) ? s1 : INT32_MAX;
+  return span_bounds(R, E, b0, a, lo, hi);
+}
+
+// Partial accumulators of one span: sum (s0, c0); maximum s0; weighted mean
+// (s0, c0) = weight, (s1, c1) = weight x value, each a Kahan pair.
+struct Partial {
+  float s0, c0, s1, c1;
+};
+
+template <int OP>
+AMR_HD void partial_init(Partial& P) {
+  P.s0 = OP == kOpMax ? -INFINITY : 0.0f;
+  P.c0 = P.s1 = P.c1 = 0.0f;
+}
+
+template <int OP>
+AMR_HD void walk_span(const TreeView& T, const Ray& R, Entry& E, int max_level, int field, int wfield, int los,
+                      Partial& P) {
+  const int64_t nc = T.ncells;
+  if (OP == kOpSum) {
+    SumVis v{T.val + (int64_t)field * nc};
+    walk_fast(T, R, E, max_level, v);
+    P.s0 = v.s;
+    P.c0 = v.c;
+  } else if (OP == kOpMax) {
+    MaxVis v{T.val + (int64_t)field * nc, -INFINITY};
+    walk_fast(T, R, E, max_level, v);
+    P.s0 = v.m;
+  } else {
+    WMeanVis v;
+    v.w = T.val + (int64_t)wfield * nc;
+    v.f0 = T.val + (int64_t)field * nc;
+    v.f1 = los ? v.f0 + nc : v.f0;
+    v.f2 = los ? v.f0 + 2 * nc : v.f0;
+    v.los = los;
+    const float n = sqrtf((float)(R.d64[0] * R.d64[0] + R.d64[1] * R.d64[1] + R.d64[2] * R.d64[2]));
+    AMR_UNROLL
+    for (int k = 0; k < 3; ++k) v.dh[k] = (float)R.d64[k] / n;
+    walk_fast(T, R, E, max_level, v);
+    P.s0 = v.sw;
+    P.c0 = v.cw;
+    P.s1 = v.sf;
+    P.c1 = v.cf;
+  }
+}
+
+// P += Q (Q is the next span along the ray).
+template <int OP>
+AMR_HD void partial_merge(Partial& P, const Partial& Q) {
+  if (OP == kOpMax) {
+    P.s0 = fmaxf(P.s0, Q.s0);
+    return;
+  }
+  kahan_add(P.s0, P.c0, Q.s0);
+  kahan_add(P.s0, P.c0, -Q.c0);
+  if (OP == kOpWMean) {
+    kahan_add(P.s1, P.c1, Q.s1);
+    kahan_add(P.s1, P.c1, -Q.c1);
+  }
+}
+
+template <int OP>
+AMR_HD void partial_finish(const Partial& P, float& out, float& aux) {
+  if (OP == kOpSum) {
+    out = P.s0 - P.c0;
+  } else if (OP == kOpMax) {
+    out = P.s0;
+  } else {
+    const float W = P.s0 - P.c0, Sf = P.s1 - P.c1;
+    out = W > 0.0f ? Sf / W : 0.0f;
+    aux = W;
+  }
 }
 
 }  // namespace amr

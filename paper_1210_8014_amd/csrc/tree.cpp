@@ -523,7 +523,7 @@ amr_status amr_render(const amr_tree* t, const amr_camera* cam, amr_op op, const
   if (o.field < 0 || o.field + ((op == AMR_WMEAN && o.los_velocity) ? 2 : 0) >= nf)
     return fail(AMR_EINVAL, "field index out of range");
   if (op == AMR_WMEAN && (o.weight_field < 0 || o.weight_field >= nf)) return fail(AMR_EINVAL, "bad weight field");
-  int v = o.variant >= 0 ? o.variant : (t->tuned_variant[op] >= 0 ? t->tuned_variant[op] : 0);
+  int v = o.variant >= 0 ? o.variant : (t->tuned_variant[op] >= 0 ? t->tuned_variant[op] : default_variant());
   if (v >= variant_count()) return fail(AMR_EINVAL, "bad variant");
   RenderArgs a;
   a.t = t->view;
@@ -543,6 +543,7 @@ amr_status amr_render(const amr_tree* t, const amr_camera* cam, amr_op op, const
 }
 
 int32_t amr_variant_count(void) { return variant_count(); }
+int32_t amr_variant_default(void) { return default_variant(); }
 const char* amr_variant_name(int32_t v) { return (v >= 0 && v < variant_count()) ? variant_name(v) : "invalid"; }
 
 amr_status amr_count_segments(const amr_tree* t, const amr_camera* cam, int32_t* counts, int64_t* total,

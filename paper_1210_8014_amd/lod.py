@@ -174,14 +174,15 @@ def render_lod(tree: Tree, cam: Camera, op: int, model: LodModel, out, workspace
 # ------------------------------------------------------------- drivers
 
 def render_levels(tree: Tree, desc: dict, levels=range(LV0, LV0 + NCLS), op: int = SUM):
-    """Plain renders of one camera at each level (device tensors)."""
+    """Plain renders of one camera at each level (device tensors), with the
+    unsplit walk that the tile render also runs."""
     import torch
 
     out = []
     for L in levels:
         cam = set_camera(dict(desc, max_level=L), tree)
         img = torch.empty(cam.W * cam.H, dtype=torch.float32, device="cuda")
-        render(tree, cam, op, img)
+        render(tree, cam, op, img, variant=0)
         out.append(img)
     return out
 

@@ -78,3 +78,24 @@ class EmuTree:
         _load().emu_trace(*self._tree_args(), _p(k4), _p(ofuv), ctypes.c_int32(cam.max_level), _p(rays),
                           ctypes.c_int64(len(rays)), _p(offs), _p(cells))
         return offs, cells[:int(offs[-1])]
+
+    def render_split(self, cam, op, K, field=0, weight=0, los=False, rays=None, with_cells=False):
+        """Split-ray path (K spans per ray, merged in span order): values,
+        aux, per-ray cell counts and, optionally, the concatenated cells."""
+        n = cam.W * cam.H if rays is None else len(rays)
+        pix = np.arange(n, dtype=np.int64) if rays is None else np.ascontiguousarray(rays, np.int64)
+        out = np.zeros(n, np.float32)
+        aux = np.zeros(n, np.float32)
+        cnt = np.zeros(n, np.int32)
+        k4, ofuv = _cam_args(cam)
+        args = (_p(k4), _p(ofuv), ctypes.c_int32(op), ctypes.c_int32(field), ctypes.c_int32(weight),
+                ctypes.c_int32(int(los)), ctypes.c_int32(cam.max_level), _p(pix), ctypes.c_int64(n))
+        tail = (ctypes.c_int32(K),)
+        _load().emu_render_split(*self._tree_args(), *args, _p(out), _p(aux), _p(cnt), None, None, *tail)
+        if not with_cells:
+            return out, aux, cnt, None
+        offs = np.zeros(n + 1, np.int64)
+        offs[1:] = np.cumsum(cnt)
+        cells = np.zeros((max(int(offs[-1]), 1), 4), np.int32)
+        _load().emu_render_split(*self._tree_args(), *args, None, None, None, _p(offs), _p(cells), *tail)
+        return out, aux, cnt, (offs, cells[:int(offs[-1])])

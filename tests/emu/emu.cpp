@@ -97,3 +97,67 @@ int emu_trace(const int32_t* child, const float* val, int64_t ncells, int32_t nf
   return 0;
 }
 }
+
+// Split rays: the K spans of each ray walked one after another and merged in
+// span order exactly as k_render_split merges its waves.  counts: cells per
+// ray summed over the spans.  With cells != NULL, also writes the cells of
+// the spans concatenated (offsets from the counts).
+// Equal-slab spans (span_setup), K of them.
+template <int OP>
+static void split_pixel(const TreeView& T, const CameraView& C, int field, int wfield, int los, int max_level, int i,
+                        int j, int K, float& o, float& x, int32_t& count, int32_t* cells) {
+  const int b0 = T.base < max_level ? T.base : max_level;
+  Partial P;
+  partial_init<OP>(P);
+  count = 0;
+  for (int w = 0; w < K; ++w) {
+    Partial Q;
+    partial_init<OP>(Q);
+    Ray R;
+    Entry E;
+    if (setup_ray(C, i, j, R, E) && span_setup(R, E, b0, K, w)) {
+      const Entry E0 = E;
+      walk_span<OP>(T, R, E, max_level, field, wfield, los, Q);
+      E = E0;
+      CountVis cv;
+      const int32_t m = walk_fast(T, R, E, max_level, cv);
+      if (cells) {
+        TraceVis tv;
+        tv.out = cells + 4 * (int64_t)count;
+        for (int k = 0; k < 3; ++k) tv.flip_bits[k] = R.flip[k] ? 1 : 0;
+        E = E0;
+        walk_fast(T, R, E, max_level, tv);
+      }
+      count += m;
+    }
+    if (w == 0)
+      P = Q;
+    else
+      partial_merge<OP>(P, Q);
+  }
+  o = 0.0f;
+  x = 0.0f;
+  partial_finish<OP>(P, o, x);
+}
+
+extern "C" int emu_render_split(const int32_t* child, const float* val, int64_t ncells, int32_t nfields, int32_t base,
+                                int32_t lmax, const int32_t* off, const int32_t* cam4, const int64_t* ofuv, int32_t op,
+                                int32_t field, int32_t wfield, int32_t los, int32_t max_level, const int64_t* pix,
+                                int64_t n, float* out, float* aux, int32_t* counts, const int64_t* offsets,
+                                int32_t* cells, int32_t K) {
+  const TreeView T = make_tree(child, val, ncells, nfields, base, lmax, off);
+  const CameraView C = make_cam(cam4, ofuv);
+  par(n, [&](int64_t r) {
+    const int i = (int)(pix[r] % C.W), j = (int)(pix[r] / C.W);
+    float o, x;
+    int32_t m;
+    int32_t* cc = cells ? cells + 4 * offsets[r] : nullptr;
+    if (op == 0) split_pixel<kOpSum>(T, C, field, wfield, los, max_level, i, j, K, o, x, m, cc);
+    else if (op == 1) split_pixel<kOpMax>(T, C, field, wfield, los, max_level, i, j, K, o, x, m, cc);
+    else split_pixel<kOpWMean>(T, C, field, wfield, los, max_level, i, j, K, o, x, m, cc);
+    if (out) out[r] = o;
+    if (aux) aux[r] = x;
+    if (counts) counts[r] = m;
+  });
+  return 0;
+}

@@ -101,3 +101,63 @@ def test_deep_levels_fp64_boundaries():
     offs, cells = R.trace(c, rays[::5])
     assert cells[:, 0].max() >= 18
     parity.compare_all(R, OT, cam, ops=("sum", "max"), trace_rays=rays[::5], what="deep")
+
+
+class SplitRenderer(EmuRenderer):
+    """The split-ray path (each ray cut into K spans at base-level planes,
+    spans merged in order): cells concatenated over the spans must equal the
+    oracle's cell sequence exactly, the maximum must be bit-identical to the
+    unsplit walk, sums agree within the parity bars."""
+
+    def __init__(self, leaves, K, restrict=None):
+        super().__init__(leaves, restrict)
+        self.K = K
+
+    def render(self, cam, op, field=0, weight=0, los=False, rays=None):
+        out, aux, cnt, _ = self.E.render_split(cam, op, self.K, field, weight, los, rays)
+        plain = self.E.render(cam, op, field, weight, los, rays, lca=2)
+        assert np.array_equal(cnt, plain[2]), "split changes the cell count"
+        if op == oracle.MAX:
+            assert np.array_equal(out.view(np.int32), plain[0].view(np.int32)), "split changes the maximum"
+        return out, aux, cnt
+
+    def trace(self, cam, rays):
+        _, _, _, (offs, cells) = self.E.render_split(cam, oracle.MAX, self.K, rays=rays, with_cells=True)
+        return offs, cells
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_split_rays_random_trees(seed):
+    rng = np.random.default_rng(50 + seed)
+    L = amrgen.random_tree(300 + seed, lmax=6, p_refine=0.4, nfields=4)
+    L.fields[1:] -= 5.0
+    OT = oracle.Tree(L)
+    cams = rand_cams(rng, 6, W=9, H=7, inside=(seed % 2 == 1)) + degenerate_cams()
+    for K in (2, 3, 4, 7):
+        R = SplitRenderer(L, K)
+        for camd in cams:
+            for ml in (OT.lmax, 3, 1):
+                d = dict(camd, max_level=ml)
+                n = d["W"] * d["H"]
+                parity.compare_all(R, OT, d, ops=("sum", "max", "wmean"), los_fields=(1, 0, True),
+                                   trace_rays=np.arange(n), what=f"split{K} seed{seed} {d['kind']} ml{ml}")
+
+
+def test_split_rays_disk_and_deep_levels():
+    L = amrgen.disk(seed=3, lmax=11, m_thr=2e-4)
+    OT = oracle.Tree(L)
+    rays = np.random.default_rng(1).choice(128 * 128, 2000, replace=False)
+    for K in (2, 4):
+        R = SplitRenderer(L, K)
+        for cam in amrgen.disk_cameras(128, 128, max_level=11):
+            parity.compare_all(R, OT, cam, ops=("sum", "max", "wmean"), rays=rays, los_fields=(1, 0, True),
+                               trace_rays=rays[:300], what=f"split{K} disk")
+    m_thr = 3e-3
+    L = amrgen.generate(amrgen.DISK, 0, 7, 20, m_thr, True, False)
+    OT = oracle.Tree(L)
+    tgt = amrgen.core_position(0, 20, m_thr, 0)
+    s = 2.0 ** -13
+    cam = amrgen.camera("persp", (tgt[0], tgt[1] - 0.8 * s, tgt[2] + 0.6 * s), tgt, (0, 0.6, 0.8), 48, 48,
+                        fov_y=0.9, max_level=-1)
+    R = SplitRenderer(L, 4)
+    parity.compare_all(R, OT, cam, ops=("sum", "max"), trace_rays=np.arange(48 * 48)[::3], what="split deep")

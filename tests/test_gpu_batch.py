@@ -1,4 +1,4 @@
-"""GPU: batched persistent hipGraph launch is bit-identical to per-image
+"""GPU: batched persistent hipGraph launch is bit-identical to unsplit per-image
 renders, on every replay; stale trees are refused; the tuners return valid
 choices that render identically."""
 import numpy as np
@@ -49,7 +49,7 @@ def test_batch_matches_single_renders_on_every_replay(op):
     for (t, c) in pairs:
         r = torch.empty(cams[c].W * cams[c].H, device="cuda")
         a = torch.empty_like(r) if op == "wmean" else None
-        amr.render(trees[t], cams[c], o, r, a, **kw)
+        amr.render(trees[t], cams[c], o, r, a, variant=0, **kw)  # the unsplit walk the batch kernel runs
         ref.append((r, a))
     torch.cuda.synchronize()
     for rep in range(3):
@@ -108,7 +108,7 @@ def test_tuners_choose_valid_configurations(tmp_path):
     a = torch.empty_like(out)
     amr.render(t, cam, amr.SUM, a)  # default variant = the tuned one
     b = torch.empty_like(out)
-    amr.render(t, cam, amr.SUM, b, variant=0)
+    amr.render(t, cam, amr.SUM, b, variant=v)
     torch.cuda.synchronize()
     assert torch.equal(a.view(torch.int32), b.view(torch.int32))
     assert amr.apply_tuning(t, cam, amr.SUM, cache=cache) == v

@@ -1,15 +1,16 @@
 """CPU check of the render kernels' grid -> pixel mapping for every variant:
 each pixel is written by exactly one lane and no lane writes outside the
 image.  Mirrors the index arithmetic of k_render (block remap over the 8
-XCDs, packets of PW x 64/PW pixels, WPB waves per block)."""
+XCDs, packets of PW x 64/PW pixels, WPB waves per block) and of
+k_render_split (one 8 x 8 packet per block, K span waves, wave 0 writes)."""
 import numpy as np
 import pytest
 
 import paper_1210_8014_amd as amr
 
-# (packet width, waves per block, XCD remap) per variant, in library order
-VARIANTS = [(8, 1, False), (8, 2, False), (8, 4, False), (16, 4, False), (32, 2, False), (8, 1, False), (8, 4, False),
-            (8, 1, False), (8, 4, True)]
+# (packet width, waves per block, XCD remap, spans per ray) per variant, in library order
+VARIANTS = [(8, 1, False, 1), (8, 2, False, 1), (8, 4, False, 1), (16, 4, False, 1), (32, 2, False, 1),
+            (8, 1, False, 1), (8, 4, False, 1), (8, 1, False, 1), (8, 4, True, 1), (8, 2, False, 2), (8, 4, False, 4)]
 
 
 def xcd_remap(b, nb):
@@ -19,7 +20,23 @@ def xcd_remap(b, nb):
     return (b % 8) * (full // 8) + b // 8
 
 
-def covered(W, H, pw, wpb, remap):
+def covered_split(W, H, k):
+    px, py = -(-W // 8), -(-H // 8)
+    hits = np.zeros(W * H, np.int64)
+    for b in range(px * py):
+        ty, tx = divmod(b, px)
+        for t in range(64 * k):
+            lane, w = t % 64, t // 64
+            i, j = tx * 8 + lane % 8, ty * 8 + lane // 8
+            if w != 0 or ty >= py or i >= W or j >= H:
+                continue
+            hits[j * W + i] += 1
+    return hits
+
+
+def covered(W, H, pw, wpb, remap, split=1):
+    if split > 1:
+        return covered_split(W, H, split)
     ph = 64 // pw
     px, py = -(-W // pw), -(-H // ph)
     blocks = -(-(px * py) // wpb)
@@ -39,16 +56,16 @@ def covered(W, H, pw, wpb, remap):
 
 def test_variant_table_matches_library():
     names = amr.variants()
-    assert len(names) == len(VARIANTS)
-    for (pw, wpb, remap), n in zip(VARIANTS, names):
-        assert n.startswith(f"p{pw}x{64 // pw}_w{wpb}_")
+    for (pw, wpb, remap, split), n in zip(VARIANTS, names):
+        head = f"p{pw}x{64 // pw}_split{split}_" if split > 1 else f"p{pw}x{64 // pw}_w{wpb}_"
+        assert n.startswith(head)
         assert n.endswith("xcdband") == remap
 
 
 @pytest.mark.parametrize("W,H", [(1, 1), (37, 23), (64, 64), (256, 256), (130, 9), (9, 130), (517, 211)])
 def test_every_pixel_written_once(W, H):
-    for pw, wpb, remap in VARIANTS:
-        assert np.all(covered(W, H, pw, wpb, remap) == 1), (W, H, pw, wpb, remap)
+    for v in VARIANTS:
+        assert np.all(covered(W, H, *v) == 1), (W, H, v)
 
 
 def test_xcd_remap_is_a_permutation():
