@@ -41,6 +41,17 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def kernel_name(variant: int, op: str) -> str:
+    """Name of the render kernel a variant launches for op (as rocprofv3 shows it)."""
+    import paper_1210_8014_amd as amr
+
+    name = amr.variants()[variant if variant >= 0 else amr.default_variant()]
+    code = {"sum": 0, "max": 1, "wmean": 2}[op]
+    if "split" in name:
+        return "k_render_split<%d, %s>" % (code, name.split("split")[1].split("_")[0])
+    return "k_render<%d, ...> (%s)" % (code, name)
+
+
 def cpu_baseline(leaves, cams_desc, seconds_target: float = 15.0):
     """The oracle, as is, on a seeded sample of the same rays."""
     import numpy as np
@@ -212,7 +223,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_render<" + dom + ">",
+            "kernel": kernel_name(args.variant, dom),
             "achieved": kern[dom]["gbs"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
