@@ -253,7 +253,7 @@ amr_status amr_set_default_variant(amr_tree* t, amr_op op, int32_t v);
  * camera-wide level from the pixel size; here a network predicts, for each
  * 16 x 16 pixel tile, the shallowest level L in 1..16 whose render stays
  * within rel_tol of the full-depth render.
- *   coarse_level  level at which the 16 probe rays per tile are walked (9)
+ *   coarse_level  level at which the 16 probe rays per tile are walked (7)
  *   quantile      level = first class whose cumulative probability >= q
  *   conf_thresh   tiles whose top class probability is below it render at
  *                 full depth (>= 1 forces full depth everywhere)

@@ -307,11 +307,17 @@ struct FeatVis {
   }
 };
 
-// One wave = 4 tiles x 16 probe rays at pixel (16 tx + 4 a + 2, 16 ty + 4 b + 2)
-// (clamped to the image), walked with the tree truncated at level lc.
-__global__ __launch_bounds__(64) void k_features(TreeView T, CameraView C, int lc, int tiles_x, int tiles_y,
-                                                 float foot_log2, uint16_t* __restrict__ feat) {
-  const int lane = threadIdx.x & 63;
+// One block = 4 tiles x 16 probe rays at pixel (16 tx + 4 a + 2, 16 ty + 4 b + 2)
+// (clamped to the image), walked with the tree truncated at level lc.  Two
+// waves walk the two spans of every probe ray (span_setup) and wave 0 adds
+// the second span's statistics to its own, so long probes do not hold the
+// launch; the statistics are sums over cells, so the split changes only
+// their rounding.
+constexpr int kFeatStats = 15;  // col, len, slg, slg2, hist[10], segments
+__global__ __launch_bounds__(128) void k_features(TreeView T, CameraView C, int lc, int tiles_x, int tiles_y,
+                                                  float foot_log2, uint16_t* __restrict__ feat) {
+  __shared__ float part[kFeatStats * 64];
+  const int lane = threadIdx.x & 63, w = (int)(threadIdx.x >> 6);
   const int tile = blockIdx.x * 4 + (lane >> 4), probe = lane & 15;
   const int ntiles = tiles_x * tiles_y;
   const int tt = tile < ntiles ? tile : ntiles - 1;
@@ -326,8 +332,25 @@ __global__ __launch_bounds__(64) void k_features(TreeView T, CameraView C, int l
   Ray R;
   Entry E;
   int32_t nseg = 0;
+  const int b0 = T.base < lc ? T.base : lc;
   const bool hit = setup_ray(C, i, j, R, E);
-  if (hit) nseg = walk_fast(T, R, E, lc, v);
+  if (hit && span_setup(R, E, b0, 2, w)) nseg = walk_fast(T, R, E, lc, v);
+  if (w == 1) {
+    part[0 * 64 + lane] = v.col;
+    part[1 * 64 + lane] = v.len;
+    part[2 * 64 + lane] = v.slg;
+    part[3 * 64 + lane] = v.slg2;
+    for (int c = 0; c < kBins; ++c) part[(4 + c) * 64 + lane] = v.hist[c];
+    part[14 * 64 + lane] = (float)nseg;
+  }
+  __syncthreads();
+  if (w == 1) return;
+  v.col += part[0 * 64 + lane];
+  v.len += part[1 * 64 + lane];
+  v.slg += part[2 * 64 + lane];
+  v.slg2 += part[3 * 64 + lane];
+  for (int c = 0; c < kBins; ++c) v.hist[c] += part[(4 + c) * 64 + lane];
+  nseg += (int32_t)part[14 * 64 + lane];
   // reduce over the 16 probes of the tile
   float cmax = v.col;
   float s[15];
@@ -456,26 +479,64 @@ __global__ void k_zero_stats(unsigned long long* s) {
 
 // ----------------------------------------------------- render and audit
 // 8 x 8 packets (inside one 16 x 16 tile), tree truncated at the tile's
-// level.  Audited tiles below full depth are also rendered at full depth in
-// the same wave; a pixel off by more than tol keeps the full-depth value
-// and is counted.
+// level, every ray walked in two spans by the block's two waves exactly as
+// the default plain render does (a tile at full depth is bit-identical to
+// it).  Audited tiles below full depth are also rendered at full depth in the
+// same block; a pixel off by more than tol keeps the full-depth value and is
+// counted.
 template <int OP>
-__global__ __launch_bounds__(64) void k_render_tiles(RenderArgs A, const int8_t* __restrict__ level,
-                                                     const uint8_t* __restrict__ audit, int tiles_x, float tol,
-                                                     unsigned long long* stats) {
-  const int lane = threadIdx.x & 63;
-  const int packet = blockIdx.x;
+__global__ __launch_bounds__(128) void k_render_tiles(
+    RenderArgs A, const int8_t* __restrict__ level, const uint8_t* __restrict__ audit, int tiles_x, float tol,
+    unsigned long long* stats) {
+  __shared__ float part[2 * 4 * 64];
+  const int lane = threadIdx.x & 63, w = (int)(threadIdx.x >> 6);
+  // The grid covers the packets twice: audited packets are walked by the
+  // first half, which is dispatched first, so their doubled work starts early
+  // instead of landing in the tail; every other packet by the second half.
+  const int np = A.packets_x * A.packets_y;
+  const bool audit_half = (int)blockIdx.x < np;
+  const int packet = audit_half ? (int)blockIdx.x : (int)blockIdx.x - np;
   const int ty = packet / A.packets_x, tx = packet - ty * A.packets_x;
   const int i = tx * 8 + (lane & 7), j = ty * 8 + (lane >> 3);
-  if (ty >= A.packets_y || i >= A.c.W || j >= A.c.H) return;
-  const int t = (j / kTile) * tiles_x + (i / kTile);
+  const bool in = ty < A.packets_y && i < A.c.W && j < A.c.H;
+  // a packet lies inside one tile: its level and audit flag are block-uniform
+  const int t = (ty * 8 / kTile) * tiles_x + (tx * 8 / kTile);
   const int L = level[t];
+  const bool aud = audit[t] && L < A.max_level;
+  if (aud != audit_half) return;  // whole block
+  Partial Pl, Pf;
+  partial_init<OP>(Pl);
+  partial_init<OP>(Pf);
+  if (in) {
+    Ray R;
+    Entry E;
+    if (setup_ray(A.c, i, j, R, E) && span_setup(R, E, A.t.base < L ? A.t.base : L, 2, w))
+      walk_span<OP>(A.t, R, E, L, A.field, A.wfield, A.los, Pl);
+    if (aud && setup_ray(A.c, i, j, R, E) &&
+        span_setup(R, E, A.t.base < A.max_level ? A.t.base : A.max_level, 2, w))
+      walk_span<OP>(A.t, R, E, A.max_level, A.field, A.wfield, A.los, Pf);
+  }
+  if (w == 1) {
+    float* q = part + lane;
+    q[0] = Pl.s0;
+    q[64] = Pl.c0;
+    q[128] = Pl.s1;
+    q[192] = Pl.c1;
+    q[256] = Pf.s0;
+    q[320] = Pf.c0;
+    q[384] = Pf.s1;
+    q[448] = Pf.c1;
+  }
+  __syncthreads();
+  if (w == 1 || !in) return;
+  const float* q = part + lane;
+  partial_merge<OP>(Pl, Partial{q[0], q[64], q[128], q[192]});
   float o = 0.f, x = 0.f;
-  NoStack S;
-  render_pixel<OP, kWalkFast>(A.t, A.c, A.field, A.wfield, A.los, L, i, j, o, x, S);
-  if (audit[t] && L < A.max_level) {
+  partial_finish<OP>(Pl, o, x);
+  if (aud) {
+    partial_merge<OP>(Pf, Partial{q[256], q[320], q[384], q[448]});
     float of = 0.f, xf = 0.f;
-    render_pixel<OP, kWalkFast>(A.t, A.c, A.field, A.wfield, A.los, A.max_level, i, j, of, xf, S);
+    partial_finish<OP>(Pf, of, xf);
     const float d = fabsf(o - of);
     const bool bad = of != 0.f ? d > tol * fabsf(of) : d != 0.f;
     if (bad) {
@@ -555,7 +616,7 @@ amr_status amr_lod_create(const amr_lod_config* cfg, uint64_t seed, amr_lod_mode
   amr_lod_model* m = alloc_model();
   if (!m) return fail(AMR_ENOMEM, "model allocation failed");
   if (cfg) m->cfg = *cfg;
-  else m->cfg = amr_lod_config{9, 0.99f, 0.5f, 1e-3f, 0.02f, 0};
+  else m->cfg = amr_lod_config{7, 0.99f, 0.5f, 1e-3f, 0.02f, 0};
   // He-normal weights from a counter-based SplitMix64 stream, zero biases
   std::vector<float> p(kParams, 0.f);
   struct L {
@@ -693,7 +754,7 @@ amr_status amr_lod_features(const amr_tree* t, const amr_camera* cam, int32_t co
   const double foot = cam->kind == 0 ? 2.0 * std::sqrt(step / fl) : 2.0 * std::sqrt(step) * 0x1.0p-28;
   const float fl2 = (float)std::log2(foot * std::ldexp(1.0, coarse_level) + 1e-30);
   const int ntiles = tx * ty;
-  hipLaunchKernelGGL(k_features, dim3((ntiles + 3) / 4), dim3(64), 0, (hipStream_t)s, t->view, camera_view(*cam),
+  hipLaunchKernelGGL(k_features, dim3((ntiles + 3) / 4), dim3(128), 0, (hipStream_t)s, t->view, camera_view(*cam),
                      coarse_level, tx, ty, fl2, feat);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? AMR_OK : fail(AMR_EHIP, hipGetErrorString(e));
@@ -826,11 +887,11 @@ amr_status amr_render_lod(const amr_tree* t, const amr_camera* cam, amr_op op, c
   a.packets_y = (cam->H + 7) / 8;
   const unsigned np = (unsigned)(a.packets_x * a.packets_y);
   if (op == AMR_SUM)
-    hipLaunchKernelGGL(k_render_tiles<kOpSum>, dim3(np), dim3(64), 0, hs, a, lev, aud, tx, c.rel_tol, st);
+    hipLaunchKernelGGL(k_render_tiles<kOpSum>, dim3(2 * np), dim3(128), 0, hs, a, lev, aud, tx, c.rel_tol, st);
   else if (op == AMR_MAX)
-    hipLaunchKernelGGL(k_render_tiles<kOpMax>, dim3(np), dim3(64), 0, hs, a, lev, aud, tx, c.rel_tol, st);
+    hipLaunchKernelGGL(k_render_tiles<kOpMax>, dim3(2 * np), dim3(128), 0, hs, a, lev, aud, tx, c.rel_tol, st);
   else
-    hipLaunchKernelGGL(k_render_tiles<kOpWMean>, dim3(np), dim3(64), 0, hs, a, lev, aud, tx, c.rel_tol, st);
+    hipLaunchKernelGGL(k_render_tiles<kOpWMean>, dim3(2 * np), dim3(128), 0, hs, a, lev, aud, tx, c.rel_tol, st);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? AMR_OK : fail(AMR_EHIP, hipGetErrorString(e));
 }

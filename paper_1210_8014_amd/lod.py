@@ -63,7 +63,7 @@ def _lib():
 
 
 def default_config() -> dict:
-    return dict(coarse_level=9, quantile=0.99, conf_thresh=0.5, rel_tol=1e-3, audit_frac=0.02, audit_seed=0)
+    return dict(coarse_level=7, quantile=0.99, conf_thresh=0.5, rel_tol=1e-3, audit_frac=0.02, audit_seed=0)
 
 
 def tiles(W: int, H: int) -> int:
@@ -175,19 +175,19 @@ def render_lod(tree: Tree, cam: Camera, op: int, model: LodModel, out, workspace
 
 def render_levels(tree: Tree, desc: dict, levels=range(LV0, LV0 + NCLS), op: int = SUM):
     """Plain renders of one camera at each level (device tensors), with the
-    unsplit walk that the tile render also runs."""
+    library's default walk (the one the tile render also runs)."""
     import torch
 
     out = []
     for L in levels:
         cam = set_camera(dict(desc, max_level=L), tree)
         img = torch.empty(cam.W * cam.H, dtype=torch.float32, device="cuda")
-        render(tree, cam, op, img, variant=0)
+        render(tree, cam, op, img)
         out.append(img)
     return out
 
 
-def make_samples(tree: Tree, desc: dict, tol: float = 1e-3, coarse_level: int = 9):
+def make_samples(tree: Tree, desc: dict, tol: float = 1e-3, coarse_level: int = 7):
     """(features [tiles, 32] int16, labels [tiles] int8) for one camera."""
     import torch
 

@@ -99,6 +99,7 @@ def main():
     ap.add_argument("--conf", type=float, default=0.5)
     ap.add_argument("--audit", type=float, default=0.02)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--model", default=None, help="evaluate this saved model instead of training one")
     ap.add_argument("--report", default=None)
     args = ap.parse_args()
 
@@ -107,19 +108,26 @@ def main():
     from . import lod
 
     torch.cuda.set_device(0)
-    t0 = time.time()
-    feat, lab = build_dataset(_range(args.train_seeds), args.cams, args.size)
-    hist = np.bincount(lab.cpu().numpy().astype(np.int64), minlength=16)
-    log(f"dataset: {feat.shape[0]} tiles, label histogram (levels 1..16) {hist.tolist()} ({time.time() - t0:.0f} s)")
     cfg = dict(lod.default_config(), quantile=args.quantile, conf_thresh=args.conf, audit_frac=args.audit)
-    model = lod.LodModel(cfg, seed=11)
     untrained = lod.LodModel(cfg, seed=11)
-    t1 = time.time()
-    curve = lod.train(model, feat, lab, steps=args.steps, batch=args.batch, lr=args.lr, lam=args.lam, log=log)
-    torch.cuda.synchronize()
-    t_train = time.time() - t1
-    log(f"trained {args.steps} steps in {t_train:.1f} s")
-    del feat, lab
+    if args.model:
+        model = lod.LodModel(path=args.model)
+        model.config = cfg
+        hist, curve, t_train = np.zeros(16, np.int64), [], 0.0
+    else:
+        t0 = time.time()
+        feat, lab = build_dataset(_range(args.train_seeds), args.cams, args.size)
+        hist = np.bincount(lab.cpu().numpy().astype(np.int64), minlength=16)
+        log(f"dataset: {feat.shape[0]} tiles, label histogram (levels 1..16) {hist.tolist()} ({time.time() - t0:.0f} s)")
+        model = lod.LodModel(cfg, seed=11)
+        t1 = time.time()
+        curve = lod.train(model, feat, lab, steps=args.steps, batch=args.batch, lr=args.lr, lam=args.lam, log=log)
+        torch.cuda.synchronize()
+        t_train = time.time() - t1
+        log(f"trained {args.steps} steps in {t_train:.1f} s")
+        del feat, lab
+        if args.out:
+            model.save(args.out)
     rows = evaluate_seeds(model, _range(args.test_seeds), args.size)
     rows_u = evaluate_seeds(untrained, _range(args.test_seeds)[:2], args.size)
     rep = dict(config=cfg, train_seeds=args.train_seeds, test_seeds=args.test_seeds, cams_per_seed=args.cams,
@@ -127,8 +135,6 @@ def main():
                batch=args.batch, lr=args.lr, lam=args.lam, train_seconds=t_train, loss_curve=curve,
                trained=summarize(rows), untrained=summarize(rows_u), per_image=rows)
     log(json.dumps({k: rep[k] for k in ("trained", "untrained")}, indent=1))
-    if args.out:
-        model.save(args.out)
     if args.report:
         with open(args.report, "w") as f:
             json.dump(rep, f, indent=1)

@@ -157,7 +157,7 @@ def _lod_setup(conf, audit, seed=0):
     m = lod.LodModel(dict(lod.default_config(), conf_thresh=conf, audit_frac=audit), seed=seed)
     n = cam.W * cam.H
     full = torch.empty(n, device="cuda")
-    amr.render(T, cam, amr.SUM, full, variant=0)  # the unsplit walk the tile render runs
+    amr.render(T, cam, amr.SUM, full)  # the default walk, which the tile render also runs
     ws = torch.empty(lod.workspace_bytes(cam.W, cam.H), dtype=torch.uint8, device="cuda")
     st = torch.zeros(8, dtype=torch.int64, device="cuda")
     return amr, lod, T, cam, m, full, ws, st
@@ -203,7 +203,7 @@ def test_forced_wrong_levels_are_caught_by_the_audit():
     lod.render_lod(T, cam, amr.SUM, m, out, ws, st, forced=forced)
     c7 = amr.set_camera(dict(amrgen.disk_camera(60.0, 200, 136), max_level=7), T)
     r7 = torch.empty_like(full)
-    amr.render(T, c7, amr.SUM, r7, variant=0)
+    amr.render(T, c7, amr.SUM, r7)
     torch.cuda.synchronize()
     assert torch.equal(out.view(torch.int32), r7.view(torch.int32))
 
