@@ -52,6 +52,34 @@ def kernel_name(variant: int, op: str) -> str:
     return "k_render<%d, ...> (%s)" % (code, name)
 
 
+def lod_leg(seed: int = 100):
+    """Learned-LOD speed-up over the default plain render with the committed
+    model on a held-out disk (seed 100, not among the training seeds 0-99), the
+    three bench cameras, op sum: times include features, network, plan, tile
+    render and the 2% audit."""
+    import numpy as np
+
+    import amrgen
+    import paper_1210_8014_amd as amr
+    from paper_1210_8014_amd import lod
+
+    if not os.path.exists(lod.MODEL_PATH):
+        return None
+    t0 = time.time()
+    tree = amr.Tree(amrgen.disk(seed=seed))
+    model = lod.LodModel(path=lod.MODEL_PATH)
+    rows = [lod.evaluate(tree, d, model, reps=10) for d in amrgen.disk_cameras(2048, 2048, max_level=16)]
+    tree.close()
+    sp = np.array([r["speedup"] for r in rows])
+    res = {"speedup_geomean": float(np.exp(np.log(sp).mean())), "speedup_per_camera": [round(float(x), 4) for x in sp],
+           "max_frac_pixels_over_1e-3": float(max(r["frac_bad"] for r in rows)),
+           "max_rel_err": float(max(r["max_rel"] for r in rows)),
+           "mean_level": float(np.mean([r["mean_level"] for r in rows])),
+           "scene": "disk seed %d (held out), 2048x2048, inclinations 0/45/90 deg, sum" % seed}
+    log(f"lod: speed-up {res['speedup_geomean']:.3f} ({time.time() - t0:.1f} s)")
+    return res
+
+
 def cpu_baseline(leaves, cams_desc, seconds_target: float = 15.0):
     """The oracle, as is, on a seeded sample of the same rays."""
     import numpy as np
@@ -94,6 +122,7 @@ def main():
                          "in one persistent launch, compared with per-image launches")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, run one 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
+    ap.add_argument("--no-lod", action="store_true", help="skip the learned-LOD leg")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build renders on one GPU only; multi-GPU runs are not supported", file=sys.stderr)
@@ -188,6 +217,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
 
+    lod_res = None
+    if not args.no_lod:
+        lod_res = lod_leg()
+
     cpu = None
     if not args.no_cpu_baseline:
         t1 = time.time()
@@ -231,6 +264,7 @@ def main():
             "traffic": traffic,
         },
         "cpu_baseline": cpu,
+        "lod": lod_res,
     }
     print(json.dumps(line), flush=True)
 
