@@ -184,6 +184,38 @@ def test_gpu_disk_full_size_sampled():
     assert np.array_equal(w1.view(np.int32), w2.view(np.int32)) and np.array_equal(x1, x2)
 
 
+@pytest.mark.slow
+def test_gpu_deepzoom_full_size_sampled():
+    """Deep zoom at full size: ~201M leaves to level 22, the eye inside the disk
+    2^-9 box from core 0, 4096^2 pixels, automatic maximum level 21, so cells
+    at levels 18..21 (FP64 chords) are crossed.  Sum and max on a seeded 1% ray
+    sample for the default and the unsplit walk; cell sequences of 1500 rays."""
+    import paper_1210_8014_amd as amr
+
+    log("generating deep-zoom scene")
+    L = amrgen.scene("deepzoom")
+    log("leaves", L.n, "lmax", L.lmax)
+    assert L.lmax == 22 and L.n > 150_000_000
+    R = _R(L)
+    log("library tree", R.T.ncells, "cells")
+    OT = oracle.Tree(L)
+    log("oracle tree", OT.nodes, "nodes")
+    del L
+    camd = amrgen.deepzoom_camera()
+    cam = R.camera(camd)
+    assert cam.max_level == 21
+    n = cam.W * cam.H
+    rays = np.sort(np.random.default_rng(5).choice(n, n // 100, replace=False))
+    for v in (-1, 0):
+        R.variant = v
+        log("variant", v)
+        res = parity.compare_all(R, OT, camd, ops=("sum", "max"), rays=rays,
+                                 trace_rays=rays[::112] if v == -1 else None, what=f"deepzoom v{v}")
+        log("  worst sum rel", res["sum"])
+    offs, cells = R.trace(cam, rays[::112])
+    assert cells[:, 0].max() >= 18
+
+
 def test_gpu_rejects_bad_arguments():
     import paper_1210_8014_amd as amr
 
