@@ -342,7 +342,7 @@ def bench_batch(args):
         "data": "synthetic",
         "config": {
             "workload": "batched: 8 disk snapshots (seeds 0-7, %d-%d leaves) x 64 orbit cameras, sides "
-                        "log-uniform in [512, 2048], op sum(rho), one persistent graph launch"
+                        "log-uniform in [512, 2048], op sum(rho), one graph launch (shape chosen by the tuner)"
                         % (min(nleaves), max(nleaves)),
             "images": len(pairs),
             "rays_per_step": rays,
@@ -354,7 +354,8 @@ def bench_batch(args):
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_batch<sum>",
+            "kernel": ("k_batch_grid<0, %d>" % (2 if "split2" in amr.batch_configs()[best] else 1))
+                      if "grid" in amr.batch_configs()[best] else "k_batch<0, ...>",
             "achieved": alg / tb / 1e9,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -208,14 +208,17 @@ int32_t amr_variant_default(void);
  * opts into outs[k] (device fp32, H x W of that camera; auxs[k] the WMEAN
  * weight plane or auxs == NULL).  The plan copies the trees' and cameras'
  * descriptions to the device, orders images largest first and owns a
- * hipGraph (queue reset + persistent kernel over a global atomic queue of
- * 64-ray packets) captured on first use.  Output pointers are fixed at
- * creation.  Every image is bit-identical to amr_render of the same image
- * with variant 0 (the unsplit walk; the batch's dynamic schedule already
- * overlaps the long rays of one image with the work of the others).
- * The trees must outlive the plan; amr_render_batch returns AMR_ESTALE if one
- * was freed.  Creation allocates device memory (AMR_ENOMEM); rendering does
- * not.  Concurrent launches of one plan race on its queue counter. */
+ * hipGraph captured on first use: either a persistent kernel over a global
+ * atomic queue of 64-ray packets (with its queue reset), or, for the "grid"
+ * configurations, one block per packet of all images dispatched in order by
+ * the hardware.  Output pointers are fixed at creation.  Every image is
+ * bit-identical to amr_render of the same image with the matching variant:
+ * variant 0 for the unsplit configurations, p8x8_split2_fast for
+ * p8x8_split2_grid.  The trees must outlive the plan; amr_render_batch returns
+ * AMR_ESTALE if one was freed.  Creation allocates device memory
+ * (AMR_ENOMEM); rendering does not.  Concurrent launches of one plan race on
+ * its queue counter; AMR_EHIP from amr_batch_set_config if a grid
+ * configuration would need more than 2^31 - 1 blocks. */
 typedef struct amr_batch amr_batch;
 amr_status amr_batch_create(const amr_tree* const* trees, int32_t ntrees, const amr_camera* cams, int32_t ncams,
                             const int32_t* pairs, int32_t npairs, amr_op op, const amr_render_opts* opts,
@@ -223,8 +226,9 @@ amr_status amr_batch_create(const amr_tree* const* trees, int32_t ntrees, const 
 amr_status amr_render_batch(amr_batch* plan, amr_stream s);
 void amr_batch_free(amr_batch* plan);
 
-/* Persistent-kernel configurations (packet shape, descent mode, waves per
- * CU, packets per queue pop), the current one, and explicit selection. */
+/* Launch configurations (packet shape, descent mode, waves per CU and
+ * packets per queue pop of the persistent kernel, or one block per packet
+ * with the rays split in spans), the current one, and explicit selection. */
 int32_t amr_batch_config_count(void);
 const char* amr_batch_config_name(int32_t c);
 int32_t amr_batch_config(const amr_batch* plan);

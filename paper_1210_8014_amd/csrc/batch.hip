@@ -3,14 +3,15 @@
 //
 // The paper renders independent images in parallel and balances them
 // dynamically: a master hands work to whichever worker is free (Sec. 3.2),
-// which pays off "for computing lots of independent images" (Sec. 3.1).  On
-// the GPU the workers are persistent waves and the master is a global atomic
-// counter over 64-ray packets of all images: a wave takes the next chunk of
-// packets until the counter passes the end.  Images are ordered largest
-// first so the tail of the queue holds small pieces.  The queue reset and the
-// persistent kernel are captured once into a hipGraph and replayed; the
+// which pays off for many independent images (Sec. 3.1).  On the GPU the
+// workers are persistent waves and the master is a global atomic counter over
+// 64-ray packets of all images: a wave takes the next chunk of packets until
+// the counter passes the end.  The grid configurations instead give every
+// packet its own block and let the hardware dispatcher hand blocks to free
+// CUs in order.  Images are ordered largest first so the tail holds small
+// pieces.  The launch is captured once into a hipGraph and replayed; the
 // per-pixel code is the same as amr_render's, so every image is bit-identical
-// to its single-image render.
+// to its single-image render with the matching variant (unsplit or split).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -40,15 +41,19 @@ struct BatchImage {
   int32_t packets_x, packets_y;
 };
 
-// Persistent-kernel shapes: packet width, descent mode, waves per CU.
+// Launch shapes: packet width, descent mode, waves per CU and packets per
+// pop of the persistent kernel; or (split > 0) one block per packet over all
+// images, dispatched in order by the hardware, each ray walked in `split`
+// spans (the same arithmetic as the split single-image variants).
 struct BatchConfig {
-  int pw, mode, waves_per_cu, chunk;
+  int pw, mode, waves_per_cu, chunk, split;
   const char* name;
 };
 constexpr BatchConfig kBatchConfigs[] = {
-    {8, kWalkFast, 16, 2, "p8x8_fast_16w_c2"}, {8, kWalkFast, 8, 2, "p8x8_fast_8w_c2"},
-    {8, kWalkFast, 32, 2, "p8x8_fast_32w_c2"}, {8, kWalkFast, 16, 8, "p8x8_fast_16w_c8"},
-    {16, kWalkFast, 16, 2, "p16x4_fast_16w_c2"}, {8, kWalkBase, 16, 2, "p8x8_base_16w_c2"},
+    {8, kWalkFast, 16, 2, 0, "p8x8_fast_16w_c2"},   {8, kWalkFast, 8, 2, 0, "p8x8_fast_8w_c2"},
+    {8, kWalkFast, 32, 2, 0, "p8x8_fast_32w_c2"},   {8, kWalkFast, 16, 8, 0, "p8x8_fast_16w_c8"},
+    {16, kWalkFast, 16, 2, 0, "p16x4_fast_16w_c2"}, {8, kWalkBase, 16, 2, 0, "p8x8_base_16w_c2"},
+    {8, kWalkFast, 0, 0, 2, "p8x8_split2_grid"},    {8, kWalkFast, 0, 0, 1, "p8x8_fast_grid"},
 };
 constexpr int kNumBatchConfigs = sizeof(kBatchConfigs) / sizeof(kBatchConfigs[0]);
 
@@ -87,6 +92,54 @@ __global__ __launch_bounds__(64) void k_batch(const BatchImage* __restrict__ img
   }
 }
 
+// One block per packet of all images (images largest first, so the long
+// pieces start early); K waves walk the K spans of each ray and merge in LDS.
+template <int OP, int K>
+__global__ __launch_bounds__(64 * K) void k_batch_grid(const BatchImage* __restrict__ imgs,
+                                                      const int64_t* __restrict__ begin, int32_t nimg) {
+  __shared__ float part[(K > 1 ? K - 1 : 1) * 4 * 64];
+  const int lane = threadIdx.x & 63, w = (int)(threadIdx.x >> 6);
+  const int64_t p = blockIdx.x;
+  int lo = 0, hi = nimg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (begin[mid] <= p) lo = mid; else hi = mid - 1;
+  }
+  const BatchImage& I = imgs[lo];
+  const int64_t q = p - begin[lo];
+  const int ty = (int)(q / I.packets_x), tx = (int)(q - (int64_t)ty * I.packets_x);
+  const int i = tx * 8 + (lane & 7), j = ty * 8 + (lane >> 3);
+  const bool in = i < I.c.W && j < I.c.H;
+  const int b0 = I.t.base < I.max_level ? I.t.base : I.max_level;
+  Partial P;
+  partial_init<OP>(P);
+  Ray R;
+  Entry E;
+  if (in && setup_ray(I.c, i, j, R, E) && span_setup(R, E, b0, K, w))
+    walk_span<OP>(I.t, R, E, I.max_level, I.field, I.wfield, I.los, P);
+  if (K > 1) {
+    if (w > 0) {
+      float* u = part + (w - 1) * 4 * 64 + lane;
+      u[0] = P.s0;
+      u[64] = P.c0;
+      u[128] = P.s1;
+      u[192] = P.c1;
+    }
+    __syncthreads();
+    if (w != 0) return;
+    for (int v = 1; v < K; ++v) {
+      const float* u = part + (v - 1) * 4 * 64 + lane;
+      partial_merge<OP>(P, Partial{u[0], u[64], u[128], u[192]});
+    }
+  }
+  if (!in) return;
+  float o = 0.0f, x = 0.0f;
+  partial_finish<OP>(P, o, x);
+  const int64_t pix = (int64_t)j * I.c.W + i;
+  I.out[pix] = o;
+  if (OP == kOpWMean && I.aux) I.aux[pix] = x;
+}
+
 __global__ void k_zero_counter(unsigned long long* c) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0;
 }
@@ -94,7 +147,11 @@ __global__ void k_zero_counter(unsigned long long* c) {
 template <int OP>
 hipError_t launch_batch_op(const BatchConfig& cfg, const BatchImage* imgs, const int64_t* begin, int nimg,
                            int64_t total, unsigned long long* counter, int grid, hipStream_t s) {
-  if (cfg.pw == 8 && cfg.mode == kWalkFast)
+  if (cfg.split == 2)
+    hipLaunchKernelGGL((k_batch_grid<OP, 2>), dim3((unsigned)total), dim3(128), 0, s, imgs, begin, nimg);
+  else if (cfg.split == 1)
+    hipLaunchKernelGGL((k_batch_grid<OP, 1>), dim3((unsigned)total), dim3(64), 0, s, imgs, begin, nimg);
+  else if (cfg.pw == 8 && cfg.mode == kWalkFast)
     hipLaunchKernelGGL((k_batch<OP, 8, kWalkFast>), dim3(grid), dim3(64), 0, s, imgs, begin, nimg, total, counter,
                        cfg.chunk);
   else if (cfg.pw == 16 && cfg.mode == kWalkFast)
@@ -167,6 +224,7 @@ struct amr_batch {
     if (e == hipSuccess) e = hipMemcpy(d_begin, begin.data(), sizeof(int64_t) * (nimg + 1), hipMemcpyHostToDevice);
     if (e != hipSuccess) return e;
     total_packets = begin[nimg];
+    if (cfg.split > 0 && total_packets > 0x7fffffffLL) return hipErrorInvalidValue;  // one block per packet
     config = c;
     grid = cfg.waves_per_cu * num_cus();
     drop_graph();

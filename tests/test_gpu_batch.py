@@ -45,12 +45,19 @@ def test_batch_matches_single_renders_on_every_replay(op):
     outs = [torch.full((cams[c].W * cams[c].H,), -7.0, device="cuda") for _, c in pairs]
     auxs = [torch.full_like(x, -7.0) for x in outs] if op == "wmean" else None
     B = amr.Batch(trees, cams, pairs, o, outs, auxs, **kw)
-    ref = []
-    for (t, c) in pairs:
-        r = torch.empty(cams[c].W * cams[c].H, device="cuda")
-        a = torch.empty_like(r) if op == "wmean" else None
-        amr.render(trees[t], cams[c], o, r, a, variant=0, **kw)  # the unsplit walk the batch kernel runs
-        ref.append((r, a))
+    split_variant = amr.variants().index("p8x8_split2_fast")
+
+    def singles(variant):
+        out = []
+        for (t, c) in pairs:
+            r = torch.empty(cams[c].W * cams[c].H, device="cuda")
+            a = torch.empty_like(r) if op == "wmean" else None
+            amr.render(trees[t], cams[c], o, r, a, variant=variant, **kw)
+            out.append((r, a))
+        return out
+
+    ref = singles(0)  # the unsplit walk of the persistent configurations
+    ref_split = singles(split_variant)
     torch.cuda.synchronize()
     for rep in range(3):
         log("replay", rep)
@@ -64,14 +71,16 @@ def test_batch_matches_single_renders_on_every_replay(op):
             if a is not None:
                 assert torch.equal(a.view(torch.int32), auxs[k].view(torch.int32))
     for cfg in range(len(amr.batch_configs())):
-        log("config", cfg, amr.batch_configs()[cfg])
+        name = amr.batch_configs()[cfg]
+        log("config", cfg, name)
         B.set_config(cfg)
         for x in outs:
             x.fill_(-7.0)
         B.run()
         torch.cuda.synchronize()
-        for k, ((r, _), x) in enumerate(zip(ref, outs)):
-            assert torch.equal(r.view(torch.int32), x.view(torch.int32)), f"config {cfg} image {k} differs"
+        want = ref_split if "split" in name else ref
+        for k, ((r, _), x) in enumerate(zip(want, outs)):
+            assert torch.equal(r.view(torch.int32), x.view(torch.int32)), f"config {name} image {k} differs"
     B.close()
 
 
