@@ -26,7 +26,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 B_SEG = {"sum": 8, "wmean": 20}   # value(s) + own first-child word per ray-cell segment
 B_PIX = {"sum": 4, "wmean": 8}    # output plane(s) per ray
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_disk.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1210_8014_amd", "csrc", f) for f in ("render.hip", "traverse.h")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1210_8014_amd", "csrc", f) for f in ("render.hip", "batch.hip", "traverse.h")]
 
 
 def log(*a):
@@ -80,6 +80,14 @@ def lod_leg(seed: int = 100):
     return res
 
 
+def batch_kernel_name(config: str, op: str) -> str:
+    """Name of the kernel a batch launch shape runs for op (as rocprofv3 shows it)."""
+    code = {"sum": 0, "max": 1, "wmean": 2}[op]
+    if "grid" in config:
+        return "k_batch_grid<%d, %d>" % (code, 2 if "split2" in config else 1)
+    return "k_batch<%d, ...> (%s)" % (code, config)
+
+
 def cpu_baseline(leaves, cams_desc, seconds_target: float = 15.0):
     """The oracle, as is, on a seeded sample of the same rays."""
     import numpy as np
@@ -123,6 +131,8 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, run one 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
     ap.add_argument("--no-lod", action="store_true", help="skip the learned-LOD leg")
+    ap.add_argument("--per-image", action="store_true",
+                    help="render the step with six single-image launches instead of two batch launches")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build renders on one GPU only; multi-GPU runs are not supported", file=sys.stderr)
@@ -160,8 +170,32 @@ def main():
 
     stream = torch.cuda.current_stream()
     ev = {"sum": [], "wmean": []}
+    batched = not args.per_image
+    plans = {}
+    if batched:
+        # one plan per op over the three cameras, launch shape chosen by the tuner (untimed)
+        pairs = [(0, k) for k in range(len(cams))]
+        plans["sum"] = amr.Batch([tree], cams, pairs, amr.SUM, [outs[2 * k] for k in range(len(cams))], field=0)
+        plans["wmean"] = amr.Batch([tree], cams, pairs, amr.WMEAN, [outs[2 * k + 1] for k in range(len(cams))],
+                                   auxs, field=1, weight=0, los=True)
+        for op, B in plans.items():
+            best, times = B.tune(reps=2)
+            log(f"{op} batch configurations (ms): " + ", ".join(f"{k} {v:.2f}" for k, v in times.items()) +
+                f"; chosen {amr.batch_configs()[best]}")
+
+    def batched_step(record: bool):
+        for op in ("sum", "wmean"):
+            if record:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+            plans[op].run()
+            if record:
+                e1.record(stream)
+                ev[op].append((-1, e0, e1))
 
     def step(record: bool):
+        if batched:
+            return batched_step(record)
         for k, c in enumerate(cams):
             if record:
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -191,18 +225,39 @@ def main():
     rays_per_step = 2 * len(cams) * npix
     value = rays_per_step / (t_wall / args.steps) / 1e6
 
+    per_image_ms = None
+    if batched:
+        # reference: the same step as six single-image launches of the default variant
+        def singles():
+            for k, c in enumerate(cams):
+                amr.render(tree, c, amr.SUM, outs[2 * k], field=0)
+                amr.render(tree, c, amr.WMEAN, outs[2 * k + 1], auxs[k], field=1, weight=0, los=True)
+        singles()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(5):
+            singles()
+        torch.cuda.synchronize()
+        per_image_ms = 1e3 * (time.perf_counter() - t1) / 5
+
+    def launch_bytes(op, k):
+        if k < 0:  # one batch launch covers all cameras
+            return sum(segs[q] * B_SEG[op] + npix * B_PIX[op] for q in range(len(cams)))
+        return segs[k] * B_SEG[op] + npix * B_PIX[op]
+
     kern = {}
     for op in ("sum", "wmean"):
         durs = [e0.elapsed_time(e1) * 1e-3 for _, e0, e1 in ev[op]]
-        byts = [segs[k] * B_SEG[op] + npix * B_PIX[op] for k, _, _ in ev[op]]
+        byts = [launch_bytes(op, k) for k, _, _ in ev[op]]
         avg_t = sum(durs) / len(durs)
         avg_b = sum(byts) / len(byts)
+        ipl = len(cams) if batched else 1  # images per launch
         kern[op] = dict(avg_ms=avg_t * 1e3, alg_bytes=avg_b, gbs=avg_b / avg_t / 1e9, total_s=sum(durs),
-                        mrays=npix / avg_t / 1e6, seg_per_s=(sum(segs) / len(segs)) / avg_t)
+                        mrays=ipl * npix / avg_t / 1e6, seg_per_s=ipl * (sum(segs) / len(segs)) / avg_t)
         log(f"{op}: avg {avg_t * 1e3:.3f} ms/launch, {kern[op]['gbs']:.0f} GB/s algorithmic, "
             f"{kern[op]['mrays']:.0f} Mrays/s, {kern[op]['seg_per_s'] / 1e9:.1f} Gseg/s")
     dom = max(kern, key=lambda k: kern[k]["total_s"])
-    alg_total = sum(kern[op]["alg_bytes"] for op in kern) * len(cams)
+    alg_total = sum(kern[op]["alg_bytes"] for op in kern) * (1 if batched else len(cams))
 
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
@@ -252,11 +307,16 @@ def main():
             "algorithmic_GBs": alg_total / (t_wall / args.steps) / 1e9,
             "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                         for k, v in kern.items()},
-            "variant": amr.variants()[args.variant if args.variant >= 0 else amr.default_variant()],
+            "launches": ("two batch launches per step (sum, wmean), three images each" if batched
+                         else "six single-image launches per step"),
+            "launch_shape": ({op: amr.batch_configs()[B.config] for op, B in plans.items()} if batched
+                             else amr.variants()[args.variant if args.variant >= 0 else amr.default_variant()]),
+            "single_image_ms_per_step": per_image_ms,
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": kernel_name(args.variant, dom),
+            "kernel": (batch_kernel_name(amr.batch_configs()[plans[dom].config], dom) if batched
+                       else kernel_name(args.variant, dom)),
             "achieved": kern[dom]["gbs"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

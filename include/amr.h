@@ -207,7 +207,9 @@ int32_t amr_variant_default(void);
  * renders tree trees[pairs[2k]] through camera cams[pairs[2k+1]] with op and
  * opts into outs[k] (device fp32, H x W of that camera; auxs[k] the WMEAN
  * weight plane or auxs == NULL).  The plan copies the trees' and cameras'
- * descriptions to the device, orders images largest first and owns a
+ * descriptions to the device, orders the images by the length of their
+ * longest ray (measured once here, one counting pass per image), then by
+ * size, largest first, and owns a
  * hipGraph captured on first use: either a persistent kernel over a global
  * atomic queue of 64-ray packets (with its queue reset), or, for the "grid"
  * configurations, one block per packet of all images dispatched in order by

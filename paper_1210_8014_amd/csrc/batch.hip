@@ -140,6 +140,25 @@ __global__ __launch_bounds__(64 * K) void k_batch_grid(const BatchImage* __restr
   if (OP == kOpWMean && I.aux) I.aux[pix] = x;
 }
 
+// Longest ray of an image, in cells (for ordering the batch).
+__global__ __launch_bounds__(256) void k_longest_ray(TreeView T, CameraView C, int max_level, unsigned* out) {
+  const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned n = 0;
+  if (pix < (int64_t)C.W * C.H) {
+    Ray R;
+    Entry E;
+    if (setup_ray(C, (int)(pix % C.W), (int)(pix / C.W), R, E)) {
+      CountVis v;
+      n = (unsigned)walk_fast(T, R, E, max_level, v);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned o = (unsigned)__shfl_down((int)n, off, 64);
+    n = o > n ? o : n;
+  }
+  if ((threadIdx.x & 63) == 0 && n) atomicMax(out, n);
+}
+
 __global__ void k_zero_counter(unsigned long long* c) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0;
 }
@@ -305,9 +324,27 @@ amr_status amr_batch_create(const amr_tree* const* trees, int32_t ntrees, const 
     I.packets_x = I.packets_y = 0;
     serials.push_back(t->serial);
   }
+  // Order: images whose longest ray is longest first (a lone wave walking it
+  // sets the end of the launch unless it starts early), then larger first.
+  std::vector<unsigned> longest(npairs, 0);
+  {
+    unsigned* d_long = nullptr;
+    hipError_t e = hipMalloc((void**)&d_long, sizeof(unsigned) * npairs);
+    if (e == hipSuccess) e = hipMemset(d_long, 0, sizeof(unsigned) * npairs);
+    for (int k = 0; k < npairs && e == hipSuccess; ++k) {
+      const int64_t n = (int64_t)imgs[k].c.W * imgs[k].c.H;
+      hipLaunchKernelGGL(k_longest_ray, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, 0, imgs[k].t, imgs[k].c,
+                         imgs[k].max_level, d_long + k);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpy(longest.data(), d_long, sizeof(unsigned) * npairs, hipMemcpyDeviceToHost);
+    if (d_long) (void)hipFree(d_long);
+    if (e != hipSuccess) return fail(AMR_EHIP, std::string("batch ordering failed: ") + hipGetErrorString(e));
+  }
   std::vector<int> order(npairs);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (longest[a] != longest[b]) return longest[a] > longest[b];
     return (int64_t)imgs[a].c.W * imgs[a].c.H > (int64_t)imgs[b].c.W * imgs[b].c.H;
   });
   amr_batch* B = new (std::nothrow) amr_batch();
