@@ -263,8 +263,10 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
-        if tr.get("kernel_hash") == kernel_hash() and dom in tr.get("per_launch_bytes", {}):
-            traffic = tr["per_launch_bytes"][dom]
+        kname = (batch_kernel_name(amr.batch_configs()[plans[dom].config], dom) if batched
+                 else kernel_name(args.variant, dom))
+        if tr.get("kernel_hash") == kernel_hash() and kname in tr.get("per_launch_bytes", {}):
+            traffic = tr["per_launch_bytes"][kname]
 
     if args.calib_copy:
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
