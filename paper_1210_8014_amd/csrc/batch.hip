@@ -224,8 +224,8 @@ struct amr_batch {
   hipGraphExec_t exec = nullptr;
 
   void drop_graph() {
-    if (exec) hipGraphExecDestroy(exec);
-    if (graph) hipGraphDestroy(graph);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
     exec = nullptr;
     graph = nullptr;
   }
@@ -411,19 +411,23 @@ amr_status amr_batch_tune(amr_batch* B, int32_t reps, int32_t* best, float* time
     if (B->use_config(c) != hipSuccess) { st = fail(AMR_EHIP, "batch upload failed"); break; }
     float tmin = 3.4e38f;
     for (int r = 0; r < reps + 1; ++r) {  // first launch warms up
-      hipEventRecord(e0, B->capture_stream);
-      if (B->enqueue(B->capture_stream) != hipSuccess) { st = fail(AMR_EHIP, "batch launch failed"); break; }
-      hipEventRecord(e1, B->capture_stream);
-      if (hipEventSynchronize(e1) != hipSuccess) { st = fail(AMR_EHIP, "batch run failed"); break; }
+      if (hipEventRecord(e0, B->capture_stream) != hipSuccess || B->enqueue(B->capture_stream) != hipSuccess ||
+          hipEventRecord(e1, B->capture_stream) != hipSuccess) {
+        st = fail(AMR_EHIP, "batch launch failed");
+        break;
+      }
       float ms = 0.0f;
-      hipEventElapsedTime(&ms, e0, e1);
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        st = fail(AMR_EHIP, "batch run failed");
+        break;
+      }
       if (r > 0 && ms < tmin) tmin = ms;
     }
     if (times_ms) times_ms[c] = tmin;
     if (tmin < bt) { bt = tmin; bi = c; }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (st != AMR_OK) return st;
   if (B->use_config(bi) != hipSuccess) return fail(AMR_EHIP, "batch upload failed");
   if (best) *best = bi;
@@ -435,10 +439,10 @@ int32_t amr_batch_config(const amr_batch* B) { return B ? B->config : -1; }
 void amr_batch_free(amr_batch* B) {
   if (!B) return;
   B->drop_graph();
-  if (B->capture_stream) hipStreamDestroy(B->capture_stream);
-  if (B->d_imgs) hipFree(B->d_imgs);
-  if (B->d_begin) hipFree(B->d_begin);
-  if (B->d_counter) hipFree(B->d_counter);
+  if (B->capture_stream) (void)hipStreamDestroy(B->capture_stream);
+  if (B->d_imgs) (void)hipFree(B->d_imgs);
+  if (B->d_begin) (void)hipFree(B->d_begin);
+  if (B->d_counter) (void)hipFree(B->d_counter);
   delete B;
 }
 
@@ -458,20 +462,22 @@ amr_status amr_tune(amr_tree* t, const amr_camera* cam, amr_op op, const amr_ren
     o.variant = v;
     float tmin = 3.4e38f;
     for (int r = 0; r < reps + 1; ++r) {
-      hipEventRecord(e0, (hipStream_t)s);
+      if (hipEventRecord(e0, (hipStream_t)s) != hipSuccess) { st = fail(AMR_EHIP, "event record failed"); break; }
       st = amr_render(t, cam, op, &o, out, aux, s);
       if (st != AMR_OK) break;
-      hipEventRecord(e1, (hipStream_t)s);
-      if (hipEventSynchronize(e1) != hipSuccess) { st = fail(AMR_EHIP, "render failed"); break; }
+      if (hipEventRecord(e1, (hipStream_t)s) != hipSuccess) { st = fail(AMR_EHIP, "event record failed"); break; }
       float ms = 0.0f;
-      hipEventElapsedTime(&ms, e0, e1);
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        st = fail(AMR_EHIP, "render failed");
+        break;
+      }
       if (r > 0 && ms < tmin) tmin = ms;
     }
     if (times_ms) times_ms[v] = tmin;
     if (tmin < bt) { bt = tmin; bi = v; }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (st != AMR_OK) return st;
   t->tuned_variant[op] = bi;
   if (best) *best = bi;

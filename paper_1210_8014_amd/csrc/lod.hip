@@ -643,11 +643,11 @@ amr_status amr_lod_create(const amr_lod_config* cfg, uint64_t seed, amr_lod_mode
 
 void amr_lod_free(amr_lod_model* m) {
   if (!m) return;
-  if (m->P) hipFree(m->P);
-  if (m->G) hipFree(m->G);
-  if (m->M) hipFree(m->M);
-  if (m->V) hipFree(m->V);
-  if (m->Wb) hipFree(m->Wb);
+  if (m->P) (void)hipFree(m->P);
+  if (m->G) (void)hipFree(m->G);
+  if (m->M) (void)hipFree(m->M);
+  if (m->V) (void)hipFree(m->V);
+  if (m->Wb) (void)hipFree(m->Wb);
   delete m;
 }
 
