@@ -468,25 +468,35 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
     ++nseg;
     const bool t0 = tie & 1, t1 = tie & 2, t2 = tie & 4;
     if ((t0 && X0 >= R.stop[0]) || (t1 && X1 >= R.stop[1]) || (t2 && X2 >= R.stop[2])) break;
-    // restart level and base-cell steps: a tied axis whose coordinate at this
-    // level ends in r one-bits carries r + 1 levels up
-    const int span = lvl - b0;
-    const int32_t bmask = (int32_t(1) << span) - 1;
-    jr = lvl - 1;
-    if (t0) {
-      const int32_t c = E.p[0] >> s;
-      jr = min(jr, lvl - 1 - (int)__builtin_ctz(~(uint32_t)c));
-      if (((c + 1) & bmask) == 0) mb = morton_step(mb, 0, f0 != 0);
-    }
-    if (t1) {
-      const int32_t c = E.p[1] >> s;
-      jr = min(jr, lvl - 1 - (int)__builtin_ctz(~(uint32_t)c));
-      if (((c + 1) & bmask) == 0) mb = morton_step(mb, 1, f1 != 0);
-    }
-    if (t2) {
-      const int32_t c = E.p[2] >> s;
-      jr = min(jr, lvl - 1 - (int)__builtin_ctz(~(uint32_t)c));
-      if (((c + 1) & bmask) == 0) mb = morton_step(mb, 2, f2 != 0);
+    // restart level and base-cell steps
+    if (lvl == b0) {
+      // a base-level cell (most cells of a typical tree): every tied axis
+      // moves the base cell, and the next cell restarts at the base level
+      jr = -1;
+      if (t0) mb = morton_step(mb, 0, f0 != 0);
+      if (t1) mb = morton_step(mb, 1, f1 != 0);
+      if (t2) mb = morton_step(mb, 2, f2 != 0);
+    } else {
+      // a tied axis whose coordinate at this level ends in r one-bits
+      // carries r + 1 levels up
+      const int span = lvl - b0;
+      const int32_t bmask = (int32_t(1) << span) - 1;
+      jr = lvl - 1;
+      if (t0) {
+        const int32_t c = E.p[0] >> s;
+        jr = min(jr, lvl - 1 - (int)__builtin_ctz(~(uint32_t)c));
+        if (((c + 1) & bmask) == 0) mb = morton_step(mb, 0, f0 != 0);
+      }
+      if (t1) {
+        const int32_t c = E.p[1] >> s;
+        jr = min(jr, lvl - 1 - (int)__builtin_ctz(~(uint32_t)c));
+        if (((c + 1) & bmask) == 0) mb = morton_step(mb, 1, f1 != 0);
+      }
+      if (t2) {
+        const int32_t c = E.p[2] >> s;
+        jr = min(jr, lvl - 1 - (int)__builtin_ctz(~(uint32_t)c));
+        if (((c + 1) & bmask) == 0) mb = morton_step(mb, 2, f2 != 0);
+      }
     }
     const int32_t keep = ~low;
     E.p[0] = t0 ? X0 : (R.d[0] > 0 ? (E.p[0] & keep) : E.p[0]);
