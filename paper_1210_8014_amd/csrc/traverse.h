@@ -114,6 +114,16 @@ AMR_HD void kahan_add(float& s, float& c, float x) {
 #define AMR_UNROLL
 #endif
 
+// Optimisation barrier: the compiler must assume x changes here, so work that
+// depends on it is not moved out of the enclosing branch.  Emits nothing.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define AMR_KEEP_HERE(x) asm volatile("" : "+v"(x))
+#else
+#define AMR_KEEP_HERE(x) \
+  do {                   \
+  } while (0)
+#endif
+
 // Per-ray constants in mirrored coordinates.
 struct Ray {
   int32_t o[3];    // mirrored origin
@@ -422,11 +432,15 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
       ++lvl;
       const int s = kFix - lvl;
       if (lvl > E.lam) {
+        // entry numerator, kept inside this rarely taken branch (hoisted, its
+        // three products would run on every cell)
+        int32_t en = E.Xa - E.oa;
+        AMR_KEEP_HERE(en);
         AMR_UNROLL
         for (int k = 0; k < 3; ++k) {
           if (E.exact & (1 << k)) continue;
           const int32_t M = E.p[k] + (int32_t(1) << s);
-          if (mul64(E.Xa - E.oa, R.d[k]) >= mul64(M - R.o[k], E.da)) E.p[k] = M;
+          if (mul64(en, R.d[k]) >= mul64(M - R.o[k], E.da)) E.p[k] = M;
         }
         E.lam = lvl;
         q0 = (uint32_t)(E.p[0] ^ f0);
