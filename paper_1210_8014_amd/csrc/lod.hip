@@ -285,8 +285,8 @@ __global__ void k_zero_f32(float* p, int n) {
 // -------------------------------------------------------------- features
 struct FeatVis {
   static constexpr bool kNeedsLength = true;
-  const float* rho;
-  const uint8_t* md;
+  const float AMR_GLOBAL* rho;
+  const uint8_t AMR_GLOBAL* md;
   float x = 0.f;
   int depth = 0;
   float col = 0.f, len = 0.f, slg = 0.f, slg2 = 0.f;

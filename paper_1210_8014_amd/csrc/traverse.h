@@ -66,10 +66,19 @@ constexpr int kMaxLevel = 24;
 constexpr int kDeepLevel = 18;
 constexpr int kMaxArithBase = 10;  // Morton code of the base level fits 30 bits
 
+// Device code sees the tree arrays as global memory, so gathers through
+// pointers read from memory (batch image tables) compile to global rather
+// than flat loads.  Host code sees plain pointers; the layout is the same.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define AMR_GLOBAL __attribute__((address_space(1)))
+#else
+#define AMR_GLOBAL
+#endif
+
 struct TreeView {
-  const int32_t* child;  // first-child index per cell, -1 for leaves
-  const float* val;      // [nfields][ncells]
-  const uint8_t* maxdepth;
+  const int32_t AMR_GLOBAL* child;  // first-child index per cell, -1 for leaves
+  const float AMR_GLOBAL* val;      // [nfields][ncells]
+  const uint8_t AMR_GLOBAL* maxdepth;
   int64_t ncells;
   int32_t nfields;
   int32_t base;  // levels 0..base are complete; base <= kMaxArithBase
@@ -538,7 +547,7 @@ AMR_HD int32_t walk_ray(const TreeView& T, const Ray& R, Entry& E, int max_level
 
 struct SumVis {
   static constexpr bool kNeedsLength = true;
-  const float* v;
+  const float AMR_GLOBAL* v;
   float s = 0.0f, c = 0.0f, x = 0.0f;
   AMR_HD void fetch(int32_t node) { x = v[node]; }
   AMR_HD void seg(int32_t, int, float len, int32_t, int32_t, int32_t) { kahan_add(s, c, x * len); }
@@ -546,7 +555,7 @@ struct SumVis {
 
 struct MaxVis {
   static constexpr bool kNeedsLength = false;
-  const float* v;
+  const float AMR_GLOBAL* v;
   float m;
   float x = 0.0f;
   AMR_HD void fetch(int32_t node) { x = v[node]; }
@@ -555,10 +564,10 @@ struct MaxVis {
 
 struct WMeanVis {
   static constexpr bool kNeedsLength = true;
-  const float* w;
-  const float* f0;
-  const float* f1;
-  const float* f2;
+  const float AMR_GLOBAL* w;
+  const float AMR_GLOBAL* f0;
+  const float AMR_GLOBAL* f1;
+  const float AMR_GLOBAL* f2;
   float dh[3];
   int los;
   float sw = 0.0f, cw = 0.0f, sf = 0.0f, cf = 0.0f;

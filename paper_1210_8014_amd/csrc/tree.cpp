@@ -367,9 +367,9 @@ amr_status amr_build_linear_octree(const amr_leaves* in, const amr_build_opts* o
     T->h_child.swap(child);
     T->h_val.swap(v32);
     T->h_maxdepth.swap(md);
-    V.child = T->h_child.data();
-    V.val = T->h_val.data();
-    V.maxdepth = T->h_maxdepth.data();
+    V.child = (const int32_t AMR_GLOBAL*)T->h_child.data();
+    V.val = (const float AMR_GLOBAL*)T->h_val.data();
+    V.maxdepth = (const uint8_t AMR_GLOBAL*)T->h_maxdepth.data();
   } else {
     int e = dev_malloc((void**)&T->d_child, ncells * 4);
     if (!e) e = dev_malloc((void**)&T->d_val, (size_t)nf * ncells * 4);
@@ -385,9 +385,9 @@ amr_status amr_build_linear_octree(const amr_leaves* in, const amr_build_opts* o
       amr_tree_free(T);
       return fail(AMR_EHIP, std::string("upload failed: ") + dev_error_string(e));
     }
-    V.child = T->d_child;
-    V.val = T->d_val;
-    V.maxdepth = T->d_maxdepth;
+    V.child = (const int32_t AMR_GLOBAL*)T->d_child;
+    V.val = (const float AMR_GLOBAL*)T->d_val;
+    V.maxdepth = (const uint8_t AMR_GLOBAL*)T->d_maxdepth;
   }
   *out = T;
   return AMR_OK;
