@@ -19,6 +19,8 @@ struct amr_tree {
   std::vector<int32_t> h_child;
   std::vector<float> h_val;
   std::vector<uint8_t> h_maxdepth;
+  std::vector<amr::Cell4> h_packed;  // fields 0..3 interleaved (nfields >= 4)
+  amr::Cell4* d_packed = nullptr;
   uint64_t serial = 0;      // unique id (batches detect freed trees)
   int32_t tuned_variant[3] = {-1, -1, -1};  // default kernel variant per op (-1: variant 0)
 };

@@ -85,6 +85,14 @@ struct TreeView {
   int32_t lmax;
   int32_t pad_;
   int32_t off[kMaxLevel + 2];  // first cell index of each level
+  // Fields 0..3 interleaved per cell (density and velocity of the usual
+  // layout), or null when the tree has fewer than 4 fields: the
+  // line-of-sight weighted mean gathers one 16-byte record per cell.
+  const struct Cell4 AMR_GLOBAL* packed;
+};
+
+struct alignas(16) Cell4 {
+  float f0, f1, f2, f3;
 };
 
 struct CameraView {
@@ -568,11 +576,20 @@ struct WMeanVis {
   const float AMR_GLOBAL* f0;
   const float AMR_GLOBAL* f1;
   const float AMR_GLOBAL* f2;
+  const Cell4 AMR_GLOBAL* pk = nullptr;  // weight = field 0, velocity = fields 1..3, interleaved
   float dh[3];
   int los;
   float sw = 0.0f, cw = 0.0f, sf = 0.0f, cf = 0.0f;
   float xw = 0.0f, x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
   AMR_HD void fetch(int32_t node) {
+    if (pk) {
+      const Cell4 q = pk[node];
+      xw = q.f0;
+      x0 = q.f1;
+      x1 = q.f2;
+      x2 = q.f3;
+      return;
+    }
     xw = w[node];
     x0 = f0[node];
     if (los) {
@@ -650,6 +667,7 @@ AMR_HD void render_pixel(const TreeView& T, const CameraView& C, int field, int 
     v.f1 = los ? v.f0 + nc : v.f0;
     v.f2 = los ? v.f0 + 2 * nc : v.f0;
     v.los = los;
+    if (los && wfield == 0 && field == 1 && T.packed) v.pk = T.packed;
     v.dh[0] = v.dh[1] = v.dh[2] = 0.0f;
     if (hit) {
       const float n = sqrtf((float)(R.d64[0] * R.d64[0] + R.d64[1] * R.d64[1] + R.d64[2] * R.d64[2]));
@@ -822,6 +840,7 @@ AMR_HD void walk_span(const TreeView& T, const Ray& R, Entry& E, int max_level, 
     v.f1 = los ? v.f0 + nc : v.f0;
     v.f2 = los ? v.f0 + 2 * nc : v.f0;
     v.los = los;
+    if (los && wfield == 0 && field == 1 && T.packed) v.pk = T.packed;
     const float n = sqrtf((float)(R.d64[0] * R.d64[0] + R.d64[1] * R.d64[1] + R.d64[2] * R.d64[2]));
     AMR_UNROLL
     for (int k = 0; k < 3; ++k) v.dh[k] = (float)R.d64[k] / n;

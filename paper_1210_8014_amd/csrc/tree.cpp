@@ -341,6 +341,14 @@ amr_status amr_build_linear_octree(const amr_leaves* in, const amr_build_opts* o
   }
   std::vector<double>().swap(v64);
   std::vector<int64_t>().swap(leaf_src);
+  std::vector<Cell4> packed;
+  if (nf >= 4) {
+    packed.resize(ncells);
+    parallel_for(ncells, [&](int64_t a, int64_t b) {
+      for (int64_t c = a; c < b; ++c)
+        packed[c] = Cell4{v32[c], v32[(size_t)ncells + c], v32[2 * (size_t)ncells + c], v32[3 * (size_t)ncells + c]};
+    });
+  }
 
   // 6. info + upload
   amr_tree_info_t& I = T->info;
@@ -353,7 +361,7 @@ amr_status amr_build_linear_octree(const amr_leaves* in, const amr_build_opts* o
   I.host_only = host_only ? 1 : 0;
   for (int l = 0; l <= kMaxLevel; ++l) I.cells_per_level[l] = count[l];
   for (int l = 0; l <= kMaxLevel + 1; ++l) I.level_offset[l] = off[l];
-  I.device_bytes = host_only ? 0 : ncells * (int64_t)(4 + 4 * nf + 1);
+  I.device_bytes = host_only ? 0 : ncells * (int64_t)(4 + 4 * nf + 1) + (int64_t)packed.size() * 16;
   TreeView& V = T->view;
   std::memset(&V, 0, sizeof(V));
   V.ncells = ncells;
@@ -367,13 +375,16 @@ amr_status amr_build_linear_octree(const amr_leaves* in, const amr_build_opts* o
     T->h_child.swap(child);
     T->h_val.swap(v32);
     T->h_maxdepth.swap(md);
+    T->h_packed.swap(packed);
     V.child = (const int32_t AMR_GLOBAL*)T->h_child.data();
     V.val = (const float AMR_GLOBAL*)T->h_val.data();
     V.maxdepth = (const uint8_t AMR_GLOBAL*)T->h_maxdepth.data();
+    V.packed = T->h_packed.empty() ? nullptr : (const Cell4 AMR_GLOBAL*)T->h_packed.data();
   } else {
     int e = dev_malloc((void**)&T->d_child, ncells * 4);
     if (!e) e = dev_malloc((void**)&T->d_val, (size_t)nf * ncells * 4);
     if (!e) e = dev_malloc((void**)&T->d_maxdepth, ncells + 64);
+    if (!e && !packed.empty()) e = dev_malloc((void**)&T->d_packed, packed.size() * sizeof(Cell4));
     if (e) {
       amr_tree_free(T);
       return fail(AMR_ENOMEM, std::string("device allocation failed: ") + dev_error_string(e));
@@ -381,6 +392,7 @@ amr_status amr_build_linear_octree(const amr_leaves* in, const amr_build_opts* o
     e = dev_upload(T->d_child, child.data(), ncells * 4);
     if (!e) e = dev_upload(T->d_val, v32.data(), (size_t)nf * ncells * 4);
     if (!e) e = dev_upload(T->d_maxdepth, md.data(), ncells);
+    if (!e && !packed.empty()) e = dev_upload(T->d_packed, packed.data(), packed.size() * sizeof(Cell4));
     if (e) {
       amr_tree_free(T);
       return fail(AMR_EHIP, std::string("upload failed: ") + dev_error_string(e));
@@ -388,6 +400,7 @@ amr_status amr_build_linear_octree(const amr_leaves* in, const amr_build_opts* o
     V.child = (const int32_t AMR_GLOBAL*)T->d_child;
     V.val = (const float AMR_GLOBAL*)T->d_val;
     V.maxdepth = (const uint8_t AMR_GLOBAL*)T->d_maxdepth;
+    V.packed = (const Cell4 AMR_GLOBAL*)T->d_packed;
   }
   *out = T;
   return AMR_OK;
@@ -398,6 +411,7 @@ void amr_tree_free(amr_tree* t) {
   unregister_tree(t->serial);
   if (t->d_child) dev_free(t->d_child);
   if (t->d_val) dev_free(t->d_val);
+  if (t->d_packed) dev_free(t->d_packed);
   if (t->d_maxdepth) dev_free(t->d_maxdepth);
   delete t;
 }
