@@ -21,6 +21,8 @@ struct amr_tree {
   std::vector<uint8_t> h_maxdepth;
   std::vector<amr::Cell4> h_packed;  // fields 0..3 interleaved (nfields >= 4)
   amr::Cell4* d_packed = nullptr;
+  std::vector<amr::ChildVal> h_cv;   // (first child, field 0) per cell
+  amr::ChildVal* d_cv = nullptr;
   uint64_t serial = 0;      // unique id (batches detect freed trees)
   int32_t tuned_variant[3] = {-1, -1, -1};  // default kernel variant per op (-1: variant 0)
 };

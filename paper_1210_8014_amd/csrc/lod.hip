@@ -295,6 +295,10 @@ struct FeatVis {
     x = rho[node];
     depth = md[node];
   }
+  __device__ void fetch0(int32_t node, float v0) {
+    x = v0;  // rho is field 0
+    depth = md[node];
+  }
   __device__ void seg(int32_t, int, float l, int32_t, int32_t, int32_t) {
     col += x * l;
     len += l;

@@ -89,10 +89,18 @@ struct TreeView {
   // layout), or null when the tree has fewer than 4 fields: the
   // line-of-sight weighted mean gathers one 16-byte record per cell.
   const struct Cell4 AMR_GLOBAL* packed;
+  // First-child index and field 0 of each cell side by side: the fast walk
+  // reads one 8-byte record per cell for both the leaf test and the value.
+  const struct ChildVal AMR_GLOBAL* cv;
 };
 
 struct alignas(16) Cell4 {
   float f0, f1, f2, f3;
+};
+
+struct alignas(8) ChildVal {
+  int32_t child;
+  float v0;
 };
 
 struct CameraView {
@@ -441,9 +449,12 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
       plv = -1;
     }
     AMR_CHECK_CELL(T, node);
-    while (lvl < max_level) {
-      const int32_t w = T.child[node];
-      if (w < 0) break;
+    float v0;
+    for (;;) {
+      const ChildVal rec = T.cv[node];
+      v0 = rec.v0;
+      const int32_t w = rec.child;
+      if (lvl >= max_level || w < 0) break;
       pfc = w;
       plv = lvl;
       ++lvl;
@@ -467,7 +478,7 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
       node = w + (int32_t)(((q0 >> s) & 1u) | (((q1 >> s) & 1u) << 1) | (((q2 >> s) & 1u) << 2));
       AMR_CHECK_CELL(T, node);
     }
-    vis.fetch(node);
+    vis.fetch0(node, v0);
     const int s = kFix - lvl;
     const int32_t low = (int32_t(1) << s) - 1;
     const int32_t X0 = (E.p[0] | low) + 1, X1 = (E.p[1] | low) + 1, X2 = (E.p[2] | low) + 1;
@@ -556,8 +567,10 @@ AMR_HD int32_t walk_ray(const TreeView& T, const Ray& R, Entry& E, int max_level
 struct SumVis {
   static constexpr bool kNeedsLength = true;
   const float AMR_GLOBAL* v;
+  bool field0 = false;  // v is field 0: the fast walk hands over the value
   float s = 0.0f, c = 0.0f, x = 0.0f;
   AMR_HD void fetch(int32_t node) { x = v[node]; }
+  AMR_HD void fetch0(int32_t node, float v0) { x = field0 ? v0 : v[node]; }
   AMR_HD void seg(int32_t, int, float len, int32_t, int32_t, int32_t) { kahan_add(s, c, x * len); }
 };
 
@@ -565,8 +578,10 @@ struct MaxVis {
   static constexpr bool kNeedsLength = false;
   const float AMR_GLOBAL* v;
   float m;
+  bool field0 = false;
   float x = 0.0f;
   AMR_HD void fetch(int32_t node) { x = v[node]; }
+  AMR_HD void fetch0(int32_t node, float v0) { x = field0 ? v0 : v[node]; }
   AMR_HD void seg(int32_t, int, float, int32_t, int32_t, int32_t) { m = fmaxf(m, x); }
 };
 
@@ -597,6 +612,7 @@ struct WMeanVis {
       x2 = f2[node];
     }
   }
+  AMR_HD void fetch0(int32_t node, float) { fetch(node); }
   AMR_HD void seg(int32_t, int, float len, int32_t, int32_t, int32_t) {
     const float wl = xw * len;
     float f = x0;
@@ -609,6 +625,7 @@ struct WMeanVis {
 struct CountVis {
   static constexpr bool kNeedsLength = false;
   AMR_HD void fetch(int32_t) {}
+  AMR_HD void fetch0(int32_t, float) {}
   AMR_HD void seg(int32_t, int, float, int32_t, int32_t, int32_t) {}
 };
 
@@ -618,6 +635,7 @@ struct TraceVis {
   int32_t* out;
   int32_t flip_bits[3];  // 1 on mirrored axes
   AMR_HD void fetch(int32_t) {}
+  AMR_HD void fetch0(int32_t, float) {}
   AMR_HD void seg(int32_t, int lvl, float, int32_t c0, int32_t c1, int32_t c2) {
     const int32_t m = (int32_t(1) << lvl) - 1;
     out[0] = lvl;
@@ -653,11 +671,11 @@ AMR_HD void render_pixel(const TreeView& T, const CameraView& C, int field, int 
   const bool hit = setup_ray(C, i, j, R, E);
   const int64_t nc = T.ncells;
   if (OP == kOpSum) {
-    SumVis v{T.val + (int64_t)field * nc};
+    SumVis v{T.val + (int64_t)field * nc, field == 0};
     if (hit) walk_mode<MODE>(T, R, E, max_level, v, S);
     out = v.s - v.c;
   } else if (OP == kOpMax) {
-    MaxVis v{T.val + (int64_t)field * nc, -INFINITY};
+    MaxVis v{T.val + (int64_t)field * nc, -INFINITY, field == 0};
     if (hit) walk_mode<MODE>(T, R, E, max_level, v, S);
     out = v.m;
   } else {
@@ -825,12 +843,12 @@ AMR_HD void walk_span(const TreeView& T, const Ray& R, Entry& E, int max_level, 
                       Partial& P) {
   const int64_t nc = T.ncells;
   if (OP == kOpSum) {
-    SumVis v{T.val + (int64_t)field * nc};
+    SumVis v{T.val + (int64_t)field * nc, field == 0};
     walk_fast(T, R, E, max_level, v);
     P.s0 = v.s;
     P.c0 = v.c;
   } else if (OP == kOpMax) {
-    MaxVis v{T.val + (int64_t)field * nc, -INFINITY};
+    MaxVis v{T.val + (int64_t)field * nc, -INFINITY, field == 0};
     walk_fast(T, R, E, max_level, v);
     P.s0 = v.m;
   } else {

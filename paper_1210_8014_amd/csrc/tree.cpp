@@ -341,6 +341,10 @@ amr_status amr_build_linear_octree(const amr_leaves* in, const amr_build_opts* o
   }
   std::vector<double>().swap(v64);
   std::vector<int64_t>().swap(leaf_src);
+  std::vector<ChildVal> cv(ncells);
+  parallel_for(ncells, [&](int64_t a, int64_t b) {
+    for (int64_t c = a; c < b; ++c) cv[c] = ChildVal{child[c], v32[c]};
+  });
   std::vector<Cell4> packed;
   if (nf >= 4) {
     packed.resize(ncells);
@@ -361,7 +365,7 @@ amr_status amr_build_linear_octree(const amr_leaves* in, const amr_build_opts* o
   I.host_only = host_only ? 1 : 0;
   for (int l = 0; l <= kMaxLevel; ++l) I.cells_per_level[l] = count[l];
   for (int l = 0; l <= kMaxLevel + 1; ++l) I.level_offset[l] = off[l];
-  I.device_bytes = host_only ? 0 : ncells * (int64_t)(4 + 4 * nf + 1) + (int64_t)packed.size() * 16;
+  I.device_bytes = host_only ? 0 : ncells * (int64_t)(4 + 4 * nf + 1 + 8) + (int64_t)packed.size() * 16;
   TreeView& V = T->view;
   std::memset(&V, 0, sizeof(V));
   V.ncells = ncells;
@@ -376,6 +380,8 @@ amr_status amr_build_linear_octree(const amr_leaves* in, const amr_build_opts* o
     T->h_val.swap(v32);
     T->h_maxdepth.swap(md);
     T->h_packed.swap(packed);
+    T->h_cv.swap(cv);
+    V.cv = (const ChildVal AMR_GLOBAL*)T->h_cv.data();
     V.child = (const int32_t AMR_GLOBAL*)T->h_child.data();
     V.val = (const float AMR_GLOBAL*)T->h_val.data();
     V.maxdepth = (const uint8_t AMR_GLOBAL*)T->h_maxdepth.data();
@@ -385,6 +391,7 @@ amr_status amr_build_linear_octree(const amr_leaves* in, const amr_build_opts* o
     if (!e) e = dev_malloc((void**)&T->d_val, (size_t)nf * ncells * 4);
     if (!e) e = dev_malloc((void**)&T->d_maxdepth, ncells + 64);
     if (!e && !packed.empty()) e = dev_malloc((void**)&T->d_packed, packed.size() * sizeof(Cell4));
+    if (!e) e = dev_malloc((void**)&T->d_cv, cv.size() * sizeof(ChildVal));
     if (e) {
       amr_tree_free(T);
       return fail(AMR_ENOMEM, std::string("device allocation failed: ") + dev_error_string(e));
@@ -393,6 +400,7 @@ amr_status amr_build_linear_octree(const amr_leaves* in, const amr_build_opts* o
     if (!e) e = dev_upload(T->d_val, v32.data(), (size_t)nf * ncells * 4);
     if (!e) e = dev_upload(T->d_maxdepth, md.data(), ncells);
     if (!e && !packed.empty()) e = dev_upload(T->d_packed, packed.data(), packed.size() * sizeof(Cell4));
+    if (!e) e = dev_upload(T->d_cv, cv.data(), cv.size() * sizeof(ChildVal));
     if (e) {
       amr_tree_free(T);
       return fail(AMR_EHIP, std::string("upload failed: ") + dev_error_string(e));
@@ -401,6 +409,7 @@ amr_status amr_build_linear_octree(const amr_leaves* in, const amr_build_opts* o
     V.val = (const float AMR_GLOBAL*)T->d_val;
     V.maxdepth = (const uint8_t AMR_GLOBAL*)T->d_maxdepth;
     V.packed = (const Cell4 AMR_GLOBAL*)T->d_packed;
+    V.cv = (const ChildVal AMR_GLOBAL*)T->d_cv;
   }
   *out = T;
   return AMR_OK;
@@ -412,6 +421,7 @@ void amr_tree_free(amr_tree* t) {
   if (t->d_child) dev_free(t->d_child);
   if (t->d_val) dev_free(t->d_val);
   if (t->d_packed) dev_free(t->d_packed);
+  if (t->d_cv) dev_free(t->d_cv);
   if (t->d_maxdepth) dev_free(t->d_maxdepth);
   delete t;
 }

@@ -10,9 +10,20 @@
 
 using namespace amr;
 
+// The (first child, field 0) records the fast walk reads, rebuilt from the
+// host arrays for each emulator call (calls come from one thread; the
+// worker threads of a call only read them).
+static const ChildVal* child_val(const int32_t* child, const float* val, int64_t ncells) {
+  static std::vector<ChildVal> cv;
+  cv.resize(ncells);
+  for (int64_t c = 0; c < ncells; ++c) cv[c] = ChildVal{child[c], val[c]};
+  return cv.data();
+}
+
 static TreeView make_tree(const int32_t* child, const float* val, int64_t ncells, int32_t nfields, int32_t base,
                           int32_t lmax, const int32_t* off) {
   TreeView T{};
+  T.cv = child_val(child, val, ncells);
   T.child = child;
   T.val = val;
   T.maxdepth = nullptr;
