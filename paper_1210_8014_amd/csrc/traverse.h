@@ -464,11 +464,14 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
         // three products would run on every cell)
         int32_t en = E.Xa - E.oa;
         AMR_KEEP_HERE(en);
+        // non-exact coordinates are known down to level lam; their lower
+        // bits are left over from earlier cells and cleared here
+        const int32_t known = ~((int32_t(1) << (kFix - E.lam)) - 1);
         AMR_UNROLL
         for (int k = 0; k < 3; ++k) {
           if (E.exact & (1 << k)) continue;
-          const int32_t M = E.p[k] + (int32_t(1) << s);
-          if (mul64(en, R.d[k]) >= mul64(M - R.o[k], E.da)) E.p[k] = M;
+          const int32_t M = (E.p[k] & known) + (int32_t(1) << s);
+          E.p[k] = mul64(en, R.d[k]) >= mul64(M - R.o[k], E.da) ? M : (E.p[k] & known);
         }
         E.lam = lvl;
         q0 = (uint32_t)(E.p[0] ^ f0);
@@ -540,10 +543,11 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
         if (((c + 1) & bmask) == 0) mb = morton_step(mb, 2, f2 != 0);
       }
     }
-    const int32_t keep = ~low;
-    E.p[0] = t0 ? X0 : (R.d[0] > 0 ? (E.p[0] & keep) : E.p[0]);
-    E.p[1] = t1 ? X1 : (R.d[1] > 0 ? (E.p[1] & keep) : E.p[1]);
-    E.p[2] = t2 ? X2 : (R.d[2] > 0 ? (E.p[2] & keep) : E.p[2]);
+    // tied axes enter the next cell at their face exactly; the others keep
+    // the current cell's prefix (bits below this level are stale from here)
+    E.p[0] = t0 ? X0 : E.p[0];
+    E.p[1] = t1 ? X1 : E.p[1];
+    E.p[2] = t2 ? X2 : E.p[2];
     const int moving = (R.d[0] > 0 ? 1 : 0) | (R.d[1] > 0 ? 2 : 0) | (R.d[2] > 0 ? 4 : 0);
     E.exact = (E.exact & ~moving) | tie;
     E.lam = lvl;
