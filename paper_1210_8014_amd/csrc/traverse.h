@@ -434,6 +434,10 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
   int plv = -1;      // level of that parent
   int jr = -1;       // restart level
   int32_t nseg = 0;
+  // per-axis copies of E.exact (lane masks, not integer bits, so that no
+  // select is spent packing and unpacking them on every cell)
+  bool ex0 = E.exact & 1, ex1 = E.exact & 2, ex2 = E.exact & 4;
+  const bool mv0 = R.d[0] > 0, mv1 = R.d[1] > 0, mv2 = R.d[2] > 0;
   for (;;) {
     uint32_t q0 = (uint32_t)(E.p[0] ^ f0), q1 = (uint32_t)(E.p[1] ^ f1), q2 = (uint32_t)(E.p[2] ^ f2);
     int lvl;
@@ -467,11 +471,14 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
         // non-exact coordinates are known down to level lam; their lower
         // bits are left over from earlier cells and cleared here
         const int32_t known = ~((int32_t(1) << (kFix - E.lam)) - 1);
+        const bool exk[3] = {ex0, ex1, ex2};
+        const int32_t dvk[3] = {dv0, dv1, dv2};
         AMR_UNROLL
         for (int k = 0; k < 3; ++k) {
-          if (E.exact & (1 << k)) continue;
+          if (exk[k]) continue;
           const int32_t M = (E.p[k] & known) + (int32_t(1) << s);
-          E.p[k] = mul64(en, R.d[k]) >= mul64(M - R.o[k], E.da) ? M : (E.p[k] & known);
+          // (a coordinate that is not exact belongs to a moving axis, where dv = d)
+          E.p[k] = mul64(en, dvk[k]) >= mul64(M - R.o[k], E.da) ? M : (E.p[k] & known);
         }
         E.lam = lvl;
         q0 = (uint32_t)(E.p[0] ^ f0);
@@ -485,17 +492,18 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
     const int s = kFix - lvl;
     const int32_t low = (int32_t(1) << s) - 1;
     const int32_t X0 = (E.p[0] | low) + 1, X1 = (E.p[1] | low) + 1, X2 = (E.p[2] | low) + 1;
-    const int32_t n0 = R.d[0] > 0 ? X0 - R.o[0] : 0x7fffffff;
-    const int32_t n1 = R.d[1] > 0 ? X1 - R.o[1] : 0x7fffffff;
-    const int32_t n2 = R.d[2] > 0 ? X2 - R.o[2] : 0x7fffffff;
+    const int32_t n0 = mv0 ? X0 - R.o[0] : 0x7fffffff;
+    const int32_t n1 = mv1 ? X1 - R.o[1] : 0x7fffffff;
+    const int32_t n2 = mv2 ? X2 - R.o[2] : 0x7fffffff;
     const int64_t c01 = mul64(n0, dv1) - mul64(n1, dv0);
     const bool p1 = c01 > 0;
     const int32_t nA = p1 ? n1 : n0, dA = p1 ? dv1 : dv0;
-    const int tieA = c01 == 0 ? 3 : (p1 ? 2 : 1);
     const int64_t c2 = mul64(nA, dv2) - mul64(n2, dA);
     const bool p2 = c2 > 0;
-    const int best = p2 ? 2 : (p1 ? 1 : 0);
-    const int tie = p2 ? 4 : (c2 == 0 ? (tieA | 4) : tieA);
+    // axes whose exit plane is reached first (several on a tie)
+    const bool t2 = c2 >= 0;
+    const bool t1 = !p2 && c01 >= 0;
+    const bool t0 = !p2 && c01 <= 0;
     const int32_t nb = p2 ? n2 : nA;
     const int32_t db = p2 ? dv2 : dA;
     const int32_t Xb = p2 ? X2 : (p1 ? X1 : X0);
@@ -511,7 +519,6 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
     }
     vis.seg(node, lvl, len, E.p[0] >> s, E.p[1] >> s, E.p[2] >> s);
     ++nseg;
-    const bool t0 = tie & 1, t1 = tie & 2, t2 = tie & 4;
     if ((t0 && X0 >= R.stop[0]) || (t1 && X1 >= R.stop[1]) || (t2 && X2 >= R.stop[2])) break;
     // restart level and base-cell steps
     if (lvl == b0) {
@@ -548,15 +555,19 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
     E.p[0] = t0 ? X0 : E.p[0];
     E.p[1] = t1 ? X1 : E.p[1];
     E.p[2] = t2 ? X2 : E.p[2];
-    const int moving = (R.d[0] > 0 ? 1 : 0) | (R.d[1] > 0 ? 2 : 0) | (R.d[2] > 0 ? 4 : 0);
-    E.exact = (E.exact & ~moving) | tie;
+    // a moving axis is exact exactly when it was crossed; a fixed axis keeps
+    // its flag (it is never crossed)
+    ex0 = t0 || (ex0 && !mv0);
+    ex1 = t1 || (ex1 && !mv1);
+    ex2 = t2 || (ex2 && !mv2);
     E.lam = lvl;
-    E.a = best;
+    E.a = p2 ? 2 : (p1 ? 1 : 0);
     E.Xa = Xb;
     E.oa = Xb - nb;
     E.da = db;
     E.inv_da = invb;
   }
+  E.exact = (ex0 ? 1 : 0) | (ex1 ? 2 : 0) | (ex2 ? 4 : 0);
   return nseg;
 }
 
