@@ -403,12 +403,13 @@ AMR_HD int32_t walk(const TreeView& T, const Ray& R, Entry& E, int max_level, Vi
   return nseg;
 }
 
-// Morton-code step of one complete-level cell along axis k (0, 1, 2) by
-// +1 or -1, on a 30-bit code (dilated-integer add / subtract).
-AMR_HD uint32_t morton_step(uint32_t m, int k, bool down) {
+// Morton-code step of one complete-level cell along axis k (0, 1, 2) by +1
+// when c is set, on a 30-bit code: with the other axes' bits set to one, an
+// increment of the whole word carries through them (the bits below k
+// included) into the axis' own bits.
+AMR_HD uint32_t morton_inc(uint32_t m, int k, bool c) {
   const uint32_t mk = 0x09249249u << k;
-  const uint32_t nk = down ? (((m & mk) - (1u << k)) & mk) : (((m | ~mk) + (1u << k)) & mk);
-  return (m & ~mk) | nk;
+  return (((m | ~mk) + (c ? 1u : 0u)) & mk) | (m & ~mk);
 }
 
 // The same walk as walk<false> (identical cells, chords and order), with
@@ -428,8 +429,13 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
   const float wk0 = R.wk[0], wk1 = R.wk[1], wk2 = R.wk[2];
   const float iv0 = R.inv_d[0], iv1 = R.inv_d[1], iv2 = R.inv_d[2];
   const int32_t f0 = R.flip[0], f1 = R.flip[1], f2 = R.flip[2];
-  uint32_t mb = morton3((uint32_t)((E.p[0] ^ f0) >> sb), (uint32_t)((E.p[1] ^ f1) >> sb),
-                        (uint32_t)((E.p[2] ^ f2) >> sb));
+  // The base cell is tracked by the Morton index of its mirrored coordinates,
+  // so a step along any axis is an increment; xor with fm (the flipped axes'
+  // bits) gives the index of the stored cell.
+  const uint32_t mask3 = (uint32_t)((uint64_t(1) << (3 * b0)) - 1);
+  const uint32_t fm = ((f0 ? 0x09249249u : 0u) | (f1 ? 0x12492492u : 0u) | (f2 ? 0x24924924u : 0u)) & mask3;
+  uint32_t mb = morton3((uint32_t)(E.p[0] >> sb), (uint32_t)(E.p[1] >> sb), (uint32_t)(E.p[2] >> sb));
+  const int32_t offb = T.off[b0];  // first cell of the complete base level
   int32_t pfc = -1;  // first-child index of the current cell's parent (-1: none cached)
   int plv = -1;      // level of that parent
   int jr = -1;       // restart level
@@ -448,7 +454,7 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
       node = pfc + (int32_t)(((q0 >> s) & 1u) | (((q1 >> s) & 1u) << 1) | (((q2 >> s) & 1u) << 2));
     } else {
       lvl = b0;
-      node = T.off[b0] + (int32_t)mb;
+      node = offb + (int32_t)(mb ^ fm);
       pfc = -1;
       plv = -1;
     }
@@ -473,12 +479,17 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
         const int32_t known = ~((int32_t(1) << (kFix - E.lam)) - 1);
         const bool exk[3] = {ex0, ex1, ex2};
         const int32_t dvk[3] = {dv0, dv1, dv2};
+        const bool mvk[3] = {mv0, mv1, mv2};
         AMR_UNROLL
         for (int k = 0; k < 3; ++k) {
           if (exk[k]) continue;
           const int32_t M = (E.p[k] & known) + (int32_t(1) << s);
-          // (a coordinate that is not exact belongs to a moving axis, where dv = d)
-          E.p[k] = mul64(en, dvk[k]) >= mul64(M - R.o[k], E.da) ? M : (E.p[k] & known);
+          // direction component: dv on a moving axis, 0 on a fixed one (formed
+          // here so that it is not kept in registers across the walk)
+          int32_t dk = dvk[k];
+          AMR_KEEP_HERE(dk);
+          dk = mvk[k] ? dk : 0;
+          E.p[k] = mul64(en, dk) >= mul64(M - R.o[k], E.da) ? M : (E.p[k] & known);
         }
         E.lam = lvl;
         q0 = (uint32_t)(E.p[0] ^ f0);
@@ -525,9 +536,9 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
       // a base-level cell (most cells of a typical tree): every tied axis
       // moves the base cell, and the next cell restarts at the base level
       jr = -1;
-      if (t0) mb = morton_step(mb, 0, f0 != 0);
-      if (t1) mb = morton_step(mb, 1, f1 != 0);
-      if (t2) mb = morton_step(mb, 2, f2 != 0);
+      mb = morton_inc(mb, 0, t0);
+      mb = morton_inc(mb, 1, t1);
+      mb = morton_inc(mb, 2, t2);
     } else {
       // a tied axis whose coordinate at this level ends in r one-bits
       // carries r + 1 levels up
@@ -537,29 +548,29 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
       if (t0) {
         const int32_t c = E.p[0] >> s;
         jr = min(jr, lvl - 1 - (int)__builtin_ctz(~(uint32_t)c));
-        if (((c + 1) & bmask) == 0) mb = morton_step(mb, 0, f0 != 0);
+        mb = morton_inc(mb, 0, ((c + 1) & bmask) == 0);
       }
       if (t1) {
         const int32_t c = E.p[1] >> s;
         jr = min(jr, lvl - 1 - (int)__builtin_ctz(~(uint32_t)c));
-        if (((c + 1) & bmask) == 0) mb = morton_step(mb, 1, f1 != 0);
+        mb = morton_inc(mb, 1, ((c + 1) & bmask) == 0);
       }
       if (t2) {
         const int32_t c = E.p[2] >> s;
         jr = min(jr, lvl - 1 - (int)__builtin_ctz(~(uint32_t)c));
-        if (((c + 1) & bmask) == 0) mb = morton_step(mb, 2, f2 != 0);
+        mb = morton_inc(mb, 2, ((c + 1) & bmask) == 0);
       }
     }
-    // tied axes enter the next cell at their face exactly; the others keep
-    // the current cell's prefix (bits below this level are stale from here)
-    E.p[0] = t0 ? X0 : E.p[0];
-    E.p[1] = t1 ? X1 : E.p[1];
-    E.p[2] = t2 ? X2 : E.p[2];
-    // a moving axis is exact exactly when it was crossed; a fixed axis keeps
-    // its flag (it is never crossed)
-    ex0 = t0 || (ex0 && !mv0);
-    ex1 = t1 || (ex1 && !mv1);
-    ex2 = t2 || (ex2 && !mv2);
+    // tied axes enter the next cell at their face exactly (X = (p | low) + 1);
+    // the others keep the current cell's prefix, their bits below this level
+    // left at one (stale from here: refinement recomputes them, for a fixed
+    // axis too, so only crossed axes are exact)
+    E.p[0] = (X0 - 1) + (t0 ? 1 : 0);
+    E.p[1] = (X1 - 1) + (t1 ? 1 : 0);
+    E.p[2] = (X2 - 1) + (t2 ? 1 : 0);
+    ex0 = t0;
+    ex1 = t1;
+    ex2 = t2;
     E.lam = lvl;
     E.a = p2 ? 2 : (p1 ? 1 : 0);
     E.Xa = Xb;
