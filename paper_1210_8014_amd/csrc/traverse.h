@@ -149,6 +149,19 @@ AMR_HD void kahan_add(float& s, float& c, float x) {
   } while (0)
 #endif
 
+// A per-lane condition evaluated here, as a lane mask in scalar registers.
+// Without it the compiler re-evaluates a comparison at each later use and
+// keeps its (wide) operands live until then.  Emits no instruction.
+#if defined(__HIP_DEVICE_COMPILE__)
+__device__ inline bool amr_mask_here(bool c) {
+  unsigned long long m = __builtin_amdgcn_ballot_w64(c);
+  asm("" : "+s"(m));
+  return __builtin_amdgcn_inverse_ballot_w64(m);
+}
+#else
+inline bool amr_mask_here(bool c) { return c; }
+#endif
+
 // Per-ray constants in mirrored coordinates.
 struct Ray {
   int32_t o[3];    // mirrored origin
@@ -506,15 +519,17 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
     const int32_t n0 = mv0 ? X0 - R.o[0] : 0x7fffffff;
     const int32_t n1 = mv1 ? X1 - R.o[1] : 0x7fffffff;
     const int32_t n2 = mv2 ? X2 - R.o[2] : 0x7fffffff;
-    const int64_t c01 = mul64(n0, dv1) - mul64(n1, dv0);
-    const bool p1 = c01 > 0;
+    // exit parameters n_k / dv_k compared by cross-multiplication (the
+    // products of 31-bit factors compare directly, no difference needed)
+    const int64_t P0 = mul64(n0, dv1), P1 = mul64(n1, dv0);
+    const bool p1 = P0 > P1, g1 = amr_mask_here(P0 >= P1);
     const int32_t nA = p1 ? n1 : n0, dA = p1 ? dv1 : dv0;
-    const int64_t c2 = mul64(nA, dv2) - mul64(n2, dA);
-    const bool p2 = c2 > 0;
+    const int64_t PA = mul64(nA, dv2), P2 = mul64(n2, dA);
+    const bool p2 = PA > P2;
     // axes whose exit plane is reached first (several on a tie)
-    const bool t2 = c2 >= 0;
-    const bool t1 = !p2 && c01 >= 0;
-    const bool t0 = !p2 && c01 <= 0;
+    const bool t2 = PA >= P2;
+    const bool t1 = !p2 && g1;
+    const bool t0 = !p2 && !p1;
     const int32_t nb = p2 ? n2 : nA;
     const int32_t db = p2 ? dv2 : dA;
     const int32_t Xb = p2 ? X2 : (p1 ? X1 : X0);
