@@ -168,7 +168,7 @@ struct Ray {
   int32_t d[3];    // |direction|, >= 0
   int32_t flip[3]; // 2^28 - 1 on mirrored axes, else 0
   int64_t d64[3];  // unmirrored direction
-  float wk[3];     // |d| 2^-28 / d_k  (chord per unit of parameter numerator)
+  float ulen;      // |d| 2^-28 (fp32)
   float inv_d[3];  // 1 / d_k
   double ulen64;   // |d| 2^-28
   int32_t stop[3]; // the fast walk ends on leaving through plane x_k = stop[k]
@@ -182,7 +182,9 @@ struct Ray {
 struct Entry {
   int32_t p[3];
   int a;
-  int32_t Xa, oa, da;
+  // the current cell's entry point has ray parameter en / da (in units of the
+  // ray's own parameter scale), entered through a face normal to axis a
+  int32_t en, da;
   float inv_da;
   int exact, lam;
 };
@@ -249,19 +251,18 @@ AMR_HD bool setup_ray(const CameraView& C, int i, int j, Ray& R, Entry& E) {
     }
   }
   E.a = a;
-  E.Xa = 0;
-  E.oa = oa;  // 0 when a < 0
-  E.da = ed;  // 1 when a < 0
+  E.en = -oa;  // 0 when a < 0
+  E.da = ed;   // 1 when a < 0
   E.exact = 7;
   E.lam = kFix;
   // chord scale factors
   const int64_t dd0 = R.d64[0] * R.d64[0] + R.d64[1] * R.d64[1] + R.d64[2] * R.d64[2];
   const float ulen = sqrtf((float)dd0) * 0x1.0p-28f;
+  R.ulen = ulen;
   R.ulen64 = sqrt((double)dd0) * 0x1.0p-28;
   AMR_UNROLL
   for (int k = 0; k < 3; ++k) {
     R.inv_d[k] = R.d[k] > 0 ? 1.0f / (float)R.d[k] : 0.0f;
-    R.wk[k] = R.d[k] > 0 ? ulen / (float)R.d[k] : 0.0f;
   }
   E.inv_da = a < 0 ? 1.0f : 1.0f / (float)ed;
   R.stop[0] = R.stop[1] = R.stop[2] = kOne;
@@ -274,6 +275,13 @@ AMR_HD float i64_to_f32(int64_t v) {
   const int32_t hi = (int32_t)(v >> 32);
   const uint32_t lo = (uint32_t)(v & 0xffffffffu);
   return fmaf((float)hi, 4294967296.0f, (float)lo);
+}
+
+// Chord length of a cell from the exact numerator N of its parameter span:
+// N |d| 2^-28 / (d_b d_a), as fp32 products in this fixed order (every walk
+// uses this one expression, so that they agree bit for bit).
+AMR_HD float chord_f32(int64_t N, float ulen, float inv_db, float inv_da) {
+  return i64_to_f32(N) * ulen * inv_db * inv_da;
 }
 
 // Ancestor stack for the restart-from-common-ancestor descent: slot l holds
@@ -301,7 +309,7 @@ AMR_HD int32_t walk(const TreeView& T, const Ray& R, Entry& E, int max_level, Vi
   const int b0 = T.base < max_level ? T.base : max_level;
   // virtual direction for axes that do not move: their exit never wins
   const int32_t dv0 = R.d[0] > 0 ? R.d[0] : 1, dv1 = R.d[1] > 0 ? R.d[1] : 1, dv2 = R.d[2] > 0 ? R.d[2] : 1;
-  const float wk0 = R.wk[0], wk1 = R.wk[1], wk2 = R.wk[2];
+  const float ulen = R.ulen;
   const float iv0 = R.inv_d[0], iv1 = R.inv_d[1], iv2 = R.inv_d[2];
   int32_t nseg = 0;
   int jr = -1;  // restart level (LCA only): the stack holds levels b0..jr of the entry point's path
@@ -336,7 +344,7 @@ AMR_HD int32_t walk(const TreeView& T, const Ray& R, Entry& E, int max_level, Vi
         for (int k = 0; k < 3; ++k) {
           if (E.exact & (1 << k)) continue;
           const int32_t M = E.p[k] + (int32_t(1) << s);
-          if (mul64(E.Xa - E.oa, R.d[k]) >= mul64(M - R.o[k], E.da)) E.p[k] = M;
+          if (mul64(E.en, R.d[k]) >= mul64(M - R.o[k], E.da)) E.p[k] = M;
         }
         E.lam = lvl;
       }
@@ -365,14 +373,12 @@ AMR_HD int32_t walk(const TreeView& T, const Ray& R, Entry& E, int max_level, Vi
     const int tie = p2 ? 4 : (c2 == 0 ? (tieA | 4) : tieA);
     const int32_t nb = p2 ? n2 : nA;
     const int32_t db = p2 ? dv2 : dA;
-    const int32_t Xb = p2 ? X2 : (p1 ? X1 : X0);
-    const float wkb = p2 ? wk2 : (p1 ? wk1 : wk0);
     const float invb = p2 ? iv2 : (p1 ? iv1 : iv0);
     // ---- chord from the exact numerator of (t_exit - t_entry) d_a d_b
-    const int64_t N = mul64(nb, E.da) - mul64(E.Xa - E.oa, db);
+    const int64_t N = mul64(nb, E.da) - mul64(E.en, db);
     float len;
     if (lvl < kDeepLevel)
-      len = i64_to_f32(N) * wkb * E.inv_da;
+      len = chord_f32(N, ulen, invb, E.inv_da);
     else
       len = (float)((double)N * R.ulen64 / ((double)E.da * (double)db));
     vis.seg(node, lvl, len, E.p[0] >> s, E.p[1] >> s, E.p[2] >> s);
@@ -408,12 +414,17 @@ AMR_HD int32_t walk(const TreeView& T, const Ray& R, Entry& E, int max_level, Vi
     }
     E.lam = lvl;
     E.a = best;
-    E.Xa = Xb;
-    E.oa = Xb - nb;
+    E.en = nb;
     E.da = db;
     E.inv_da = invb;
   }
   return nseg;
+}
+
+// Octant (bit 0 = x, bit 1 = y, bit 2 = z) of the coordinates' bits at
+// position s, s >= 2.
+AMR_HD uint32_t octant_bits(int32_t x, int32_t y, int32_t z, int s) {
+  return (((uint32_t)x >> s) & 1u) | (((uint32_t)y >> (s - 1)) & 2u) | (((uint32_t)z >> (s - 2)) & 4u);
 }
 
 // Morton-code step of one complete-level cell along axis k (0, 1, 2) by +1
@@ -439,14 +450,16 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
   const int b0 = T.base < max_level ? T.base : max_level;
   const int sb = kFix - b0;
   const int32_t dv0 = R.d[0] > 0 ? R.d[0] : 1, dv1 = R.d[1] > 0 ? R.d[1] : 1, dv2 = R.d[2] > 0 ? R.d[2] : 1;
-  const float wk0 = R.wk[0], wk1 = R.wk[1], wk2 = R.wk[2];
+  const float ulen = R.ulen;
   const float iv0 = R.inv_d[0], iv1 = R.inv_d[1], iv2 = R.inv_d[2];
   const int32_t f0 = R.flip[0], f1 = R.flip[1], f2 = R.flip[2];
   // The base cell is tracked by the Morton index of its mirrored coordinates,
   // so a step along any axis is an increment; xor with fm (the flipped axes'
   // bits) gives the index of the stored cell.
+  // Its low three bits are the flipped axes as an octant mask: the child of a
+  // stored cell holding mirrored octant o is child o ^ (fm & 7).
   const uint32_t mask3 = (uint32_t)((uint64_t(1) << (3 * b0)) - 1);
-  const uint32_t fm = ((f0 ? 0x09249249u : 0u) | (f1 ? 0x12492492u : 0u) | (f2 ? 0x24924924u : 0u)) & mask3;
+  const uint32_t fm = (f0 ? 0x09249249u : 0u) | (f1 ? 0x12492492u : 0u) | (f2 ? 0x24924924u : 0u);
   uint32_t mb = morton3((uint32_t)(E.p[0] >> sb), (uint32_t)(E.p[1] >> sb), (uint32_t)(E.p[2] >> sb));
   const int32_t offb = T.off[b0];  // first cell of the complete base level
   int32_t pfc = -1;  // first-child index of the current cell's parent (-1: none cached)
@@ -458,16 +471,15 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
   bool ex0 = E.exact & 1, ex1 = E.exact & 2, ex2 = E.exact & 4;
   const bool mv0 = R.d[0] > 0, mv1 = R.d[1] > 0, mv2 = R.d[2] > 0;
   for (;;) {
-    uint32_t q0 = (uint32_t)(E.p[0] ^ f0), q1 = (uint32_t)(E.p[1] ^ f1), q2 = (uint32_t)(E.p[2] ^ f2);
     int lvl;
     int32_t node;
     if (jr >= 0 && jr == plv) {
       lvl = jr + 1;  // sibling of the previous cell
       const int s = kFix - lvl;
-      node = pfc + (int32_t)(((q0 >> s) & 1u) | (((q1 >> s) & 1u) << 1) | (((q2 >> s) & 1u) << 2));
+      node = pfc + (int32_t)(octant_bits(E.p[0], E.p[1], E.p[2], s) ^ (fm & 7u));
     } else {
       lvl = b0;
-      node = offb + (int32_t)(mb ^ fm);
+      node = offb + (int32_t)((mb ^ fm) & mask3);
       pfc = -1;
       plv = -1;
     }
@@ -485,7 +497,7 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
       if (lvl > E.lam) {
         // entry numerator, kept inside this rarely taken branch (hoisted, its
         // three products would run on every cell)
-        int32_t en = E.Xa - E.oa;
+        int32_t en = E.en;
         AMR_KEEP_HERE(en);
         // non-exact coordinates are known down to level lam; their lower
         // bits are left over from earlier cells and cleared here
@@ -505,11 +517,8 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
           E.p[k] = mul64(en, dk) >= mul64(M - R.o[k], E.da) ? M : (E.p[k] & known);
         }
         E.lam = lvl;
-        q0 = (uint32_t)(E.p[0] ^ f0);
-        q1 = (uint32_t)(E.p[1] ^ f1);
-        q2 = (uint32_t)(E.p[2] ^ f2);
       }
-      node = w + (int32_t)(((q0 >> s) & 1u) | (((q1 >> s) & 1u) << 1) | (((q2 >> s) & 1u) << 2));
+      node = w + (int32_t)(octant_bits(E.p[0], E.p[1], E.p[2], s) ^ (fm & 7u));
       AMR_CHECK_CELL(T, node);
     }
     vis.fetch0(node, v0);
@@ -532,14 +541,12 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
     const bool t0 = !p2 && !p1;
     const int32_t nb = p2 ? n2 : nA;
     const int32_t db = p2 ? dv2 : dA;
-    const int32_t Xb = p2 ? X2 : (p1 ? X1 : X0);
     const float invb = p2 ? iv2 : (p1 ? iv1 : iv0);
     float len = 0.0f;
     if (Vis::kNeedsLength) {
-      const float wkb = p2 ? wk2 : (p1 ? wk1 : wk0);
-      const int64_t N = mul64(nb, E.da) - mul64(E.Xa - E.oa, db);
+      const int64_t N = mul64(nb, E.da) - mul64(E.en, db);
       if (lvl < kDeepLevel)
-        len = i64_to_f32(N) * wkb * E.inv_da;
+        len = chord_f32(N, ulen, invb, E.inv_da);
       else
         len = (float)((double)N * R.ulen64 / ((double)E.da * (double)db));
     }
@@ -588,8 +595,7 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
     ex2 = t2;
     E.lam = lvl;
     E.a = p2 ? 2 : (p1 ? 1 : 0);
-    E.Xa = Xb;
-    E.oa = Xb - nb;
+    E.en = nb;
     E.da = db;
     E.inv_da = invb;
   }
@@ -806,8 +812,7 @@ AMR_HD bool plane_entry(const Ray& R, int a, int32_t P, Entry& E) {
   E.p[1] = p[1];
   E.p[2] = p[2];
   E.a = a;
-  E.Xa = P;
-  E.oa = oa;
+  E.en = P - oa;
   E.da = da32;
   E.inv_da = pick3(a, R.inv_d);
   E.exact = 7;
