@@ -332,7 +332,7 @@ AMR_HD int32_t walk(const TreeView& T, const Ray& R, Entry& E, int max_level, Vi
     }
     AMR_CHECK_CELL(T, node);
     while (lvl < max_level) {
-      const int32_t w = T.child[node];
+      const int32_t w = T.child[(uint32_t)node];
       if (w < 0) break;
       if (LCA) S.set(lvl, w);
       ++lvl;
@@ -443,13 +443,22 @@ AMR_HD uint32_t morton_inc(uint32_t m, int k, bool c) {
 //  - the first-child index of the current cell's parent stays in a
 //    register, so moving to a sibling (about half of all moves) skips the
 //    descent from the base level;
-//  - the unmirrored coordinates are formed once per cell, not per level;
+//  - child octants are taken from the mirrored coordinates and corrected by
+//    one xor with the flipped axes, with no unmirrored copy;
+//  - the exit face is decided on lane masks and cross-products compared
+//    directly, and the state update needs no selects (bits below the
+//    current level are left stale and refined when a deeper cell needs
+//    them);
 //  - visitors that do not use chord lengths skip their arithmetic.
 template <class Vis>
 AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_level, Vis& vis) {
   const int b0 = T.base < max_level ? T.base : max_level;
   const int sb = kFix - b0;
-  const int32_t dv0 = R.d[0] > 0 ? R.d[0] : 1, dv1 = R.d[1] > 0 ? R.d[1] : 1, dv2 = R.d[2] > 0 ? R.d[2] : 1;
+  // Direction components, 0 on an axis the ray does not move along: in the
+  // cross-multiplied comparisons below such an axis then never exits first
+  // (n_j * 0 < n_k * d_j for every moving axis j, as every n > 0), and the
+  // refinement of its coordinate bits sees d = 0 as it should.
+  const int32_t dv0 = R.d[0], dv1 = R.d[1], dv2 = R.d[2];
   const float ulen = R.ulen;
   const float iv0 = R.inv_d[0], iv1 = R.inv_d[1], iv2 = R.inv_d[2];
   const int32_t f0 = R.flip[0], f1 = R.flip[1], f2 = R.flip[2];
@@ -469,7 +478,6 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
   // per-axis copies of E.exact (lane masks, not integer bits, so that no
   // select is spent packing and unpacking them on every cell)
   bool ex0 = E.exact & 1, ex1 = E.exact & 2, ex2 = E.exact & 4;
-  const bool mv0 = R.d[0] > 0, mv1 = R.d[1] > 0, mv2 = R.d[2] > 0;
   for (;;) {
     int lvl;
     int32_t node;
@@ -486,7 +494,7 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
     AMR_CHECK_CELL(T, node);
     float v0;
     for (;;) {
-      const ChildVal rec = T.cv[node];
+      const ChildVal rec = T.cv[(uint32_t)node];
       v0 = rec.v0;
       const int32_t w = rec.child;
       if (lvl >= max_level || w < 0) break;
@@ -504,17 +512,11 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
         const int32_t known = ~((int32_t(1) << (kFix - E.lam)) - 1);
         const bool exk[3] = {ex0, ex1, ex2};
         const int32_t dvk[3] = {dv0, dv1, dv2};
-        const bool mvk[3] = {mv0, mv1, mv2};
         AMR_UNROLL
         for (int k = 0; k < 3; ++k) {
           if (exk[k]) continue;
           const int32_t M = (E.p[k] & known) + (int32_t(1) << s);
-          // direction component: dv on a moving axis, 0 on a fixed one (formed
-          // here so that it is not kept in registers across the walk)
-          int32_t dk = dvk[k];
-          AMR_KEEP_HERE(dk);
-          dk = mvk[k] ? dk : 0;
-          E.p[k] = mul64(en, dk) >= mul64(M - R.o[k], E.da) ? M : (E.p[k] & known);
+          E.p[k] = mul64(en, dvk[k]) >= mul64(M - R.o[k], E.da) ? M : (E.p[k] & known);
         }
         E.lam = lvl;
       }
@@ -525,9 +527,7 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
     const int s = kFix - lvl;
     const int32_t low = (int32_t(1) << s) - 1;
     const int32_t X0 = (E.p[0] | low) + 1, X1 = (E.p[1] | low) + 1, X2 = (E.p[2] | low) + 1;
-    const int32_t n0 = mv0 ? X0 - R.o[0] : 0x7fffffff;
-    const int32_t n1 = mv1 ? X1 - R.o[1] : 0x7fffffff;
-    const int32_t n2 = mv2 ? X2 - R.o[2] : 0x7fffffff;
+    const int32_t n0 = X0 - R.o[0], n1 = X1 - R.o[1], n2 = X2 - R.o[2];
     // exit parameters n_k / dv_k compared by cross-multiplication (the
     // products of 31-bit factors compare directly, no difference needed)
     const int64_t P0 = mul64(n0, dv1), P1 = mul64(n1, dv0);
@@ -616,8 +616,8 @@ struct SumVis {
   const float AMR_GLOBAL* v;
   bool field0 = false;  // v is field 0: the fast walk hands over the value
   float s = 0.0f, c = 0.0f, x = 0.0f;
-  AMR_HD void fetch(int32_t node) { x = v[node]; }
-  AMR_HD void fetch0(int32_t node, float v0) { x = field0 ? v0 : v[node]; }
+  AMR_HD void fetch(int32_t node) { x = v[(uint32_t)node]; }
+  AMR_HD void fetch0(int32_t node, float v0) { x = field0 ? v0 : v[(uint32_t)node]; }
   AMR_HD void seg(int32_t, int, float len, int32_t, int32_t, int32_t) { kahan_add(s, c, x * len); }
 };
 
@@ -627,8 +627,8 @@ struct MaxVis {
   float m;
   bool field0 = false;
   float x = 0.0f;
-  AMR_HD void fetch(int32_t node) { x = v[node]; }
-  AMR_HD void fetch0(int32_t node, float v0) { x = field0 ? v0 : v[node]; }
+  AMR_HD void fetch(int32_t node) { x = v[(uint32_t)node]; }
+  AMR_HD void fetch0(int32_t node, float v0) { x = field0 ? v0 : v[(uint32_t)node]; }
   AMR_HD void seg(int32_t, int, float, int32_t, int32_t, int32_t) { m = fmaxf(m, x); }
 };
 
@@ -645,18 +645,18 @@ struct WMeanVis {
   float xw = 0.0f, x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
   AMR_HD void fetch(int32_t node) {
     if (pk) {
-      const Cell4 q = pk[node];
+      const Cell4 q = pk[(uint32_t)node];
       xw = q.f0;
       x0 = q.f1;
       x1 = q.f2;
       x2 = q.f3;
       return;
     }
-    xw = w[node];
-    x0 = f0[node];
+    xw = w[(uint32_t)node];
+    x0 = f0[(uint32_t)node];
     if (los) {
-      x1 = f1[node];
-      x2 = f2[node];
+      x1 = f1[(uint32_t)node];
+      x2 = f2[(uint32_t)node];
     }
   }
   AMR_HD void fetch0(int32_t node, float) { fetch(node); }
