@@ -189,13 +189,15 @@ typedef struct {
  * the default, cut every ray into spans at base-level planes, walk the
  * spans on different waves and merge their Kahan sums in span order: their
  * SUM and WMEAN differ from the unsplit walk by rounding only and are
- * themselves deterministic. */
+ * themselves deterministic.  Variants named "center" only dispatch the
+ * packet rows from the middle of the image out; their results equal those
+ * of the same variant without it, bit for bit. */
 amr_status amr_render(const amr_tree* t, const amr_camera* cam, amr_op op, const amr_render_opts* opts, float* out,
                       float* aux, amr_stream s);
 
 /* Number of kernel variants (ray-packet shape, waves per block, descent
- * mode, spans per ray) amr_render_opts.variant may select, a short name for
- * each, and the one used when none is selected or tuned. */
+ * mode, spans per ray, dispatch order) amr_render_opts.variant may select, a
+ * short name for each, and the one used when none is selected or tuned. */
 int32_t amr_variant_count(void);
 const char* amr_variant_name(int32_t v);
 int32_t amr_variant_default(void);

@@ -43,6 +43,17 @@ struct RenderArgs {
   int32_t packets_x, packets_y;
 };
 
+// Packet index of the b-th dispatched packet (b < px * py) when packet rows
+// go out from the middle row of the image (middle, one above, one below,
+// ...): the rays that cross the most cells usually look through the middle
+// of the image, and started first their walks overlap the rest of the image
+// instead of finishing alone at its end.
+AMR_HD inline int center_out(int b, int px, int py) {
+  const int k = b / px, x = b - k * px;
+  const int row = py / 2 + ((k & 1) ? -((k + 1) >> 1) : (k >> 1));
+  return row * px + x;
+}
+
 // Kernel launchers (render.hip).  Return a hipError_t as int.
 int launch_render(int op, int variant, const RenderArgs& a, void* stream);
 int launch_count_all(const TreeView& t, const CameraView& c, int32_t* counts, int64_t* total, void* stream);

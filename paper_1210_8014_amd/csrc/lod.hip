@@ -497,9 +497,11 @@ __global__ __launch_bounds__(128) void k_render_tiles(
   // The grid covers the packets twice: audited packets are walked by the
   // first half, which is dispatched first, so their doubled work starts early
   // instead of landing in the tail; every other packet by the second half.
+  // Each half takes the packet rows from the middle of the image out, as the
+  // default plain render does.
   const int np = A.packets_x * A.packets_y;
   const bool audit_half = (int)blockIdx.x < np;
-  const int packet = audit_half ? (int)blockIdx.x : (int)blockIdx.x - np;
+  const int packet = center_out(audit_half ? (int)blockIdx.x : (int)blockIdx.x - np, A.packets_x, A.packets_y);
   const int ty = packet / A.packets_x, tx = packet - ty * A.packets_x;
   const int i = tx * 8 + (lane & 7), j = ty * 8 + (lane >> 3);
   const bool in = ty < A.packets_y && i < A.c.W && j < A.c.H;

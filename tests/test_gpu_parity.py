@@ -84,7 +84,7 @@ def test_gpu_random_trees_and_degenerate_rays(seed):
                                trace_rays=np.arange(d["W"] * d["H"]), what=f"seed{seed} cam{k} ml{ml}")
 
 
-@pytest.mark.parametrize("name", ["p8x8_split2_fast", "p8x8_split4_fast"])
+@pytest.mark.parametrize("name", ["p8x8_split2_fast", "p8x8_split4_fast", "p8x8_split2_fast_center"])
 def test_gpu_split_rays_random_trees(name):
     """Rays cut into spans at base-level planes, one wave per span: every
     result against the oracle, including degenerate and inside cameras."""
@@ -169,9 +169,16 @@ def test_gpu_disk_full_size_sampled():
     cam = R.camera(amrgen.disk_cameras()[1])
     a, _ = R.full(cam, amr.SUM, variant=0)
     am, _ = R.full(cam, amr.MAX, variant=0)
-    for v in range(len(amr.variants())):
+    names = amr.variants()
+    by_name = {}
+    for v in range(len(names)):
         log("disk variant", v)
         b, _ = R.full(cam, amr.SUM, variant=v)
+        by_name[names[v]] = b
+        if names[v].endswith("_center"):
+            # dispatch order only: equal to the same variant in plain order
+            plain = by_name[names[v][: -len("_center")]]
+            assert np.array_equal(plain.view(np.int32), b.view(np.int32)), f"variant {v} differs from plain order"
         if _is_split(v):
             # spans merged in order: same cells, sums differ by rounding only
             assert np.all(np.abs(b.astype(np.float64) - a) <= 2e-6 * np.abs(a)), f"variant {v} differs"
