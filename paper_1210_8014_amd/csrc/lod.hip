@@ -487,12 +487,15 @@ __global__ void k_zero_stats(unsigned long long* s) {
 // the default plain render does (a tile at full depth is bit-identical to
 // it).  Audited tiles below full depth are also rendered at full depth in the
 // same block; a pixel off by more than tol keeps the full-depth value and is
-// counted.
+// counted.  The two walks of an audited block run one after the other and
+// the first one's partial sums wait in LDS, so that the kernel holds the
+// registers of one walk only.
 template <int OP>
 __global__ __launch_bounds__(128) void k_render_tiles(
     RenderArgs A, const int8_t* __restrict__ level, const uint8_t* __restrict__ audit, int tiles_x, float tol,
     unsigned long long* stats) {
-  __shared__ float part[2 * 4 * 64];
+  __shared__ float full_part[2 * 4 * 64];  // full-depth partials of both span waves
+  __shared__ float part[4 * 64];           // level-L partials of span wave 1
   const int lane = threadIdx.x & 63, w = (int)(threadIdx.x >> 6);
   // The grid covers the packets twice: audited packets are walked by the
   // first half, which is dispatched first, so their doubled work starts early
@@ -510,17 +513,27 @@ __global__ __launch_bounds__(128) void k_render_tiles(
   const int L = level[t];
   const bool aud = audit[t] && L < A.max_level;
   if (aud != audit_half) return;  // whole block
-  Partial Pl, Pf;
-  partial_init<OP>(Pl);
-  partial_init<OP>(Pf);
-  if (in) {
+  if (aud) {
+    Partial Pf;
+    partial_init<OP>(Pf);
     Ray R;
     Entry E;
-    if (setup_ray(A.c, i, j, R, E) && span_setup(R, E, A.t.base < L ? A.t.base : L, 2, w))
-      walk_span<OP>(A.t, R, E, L, A.field, A.wfield, A.los, Pl);
-    if (aud && setup_ray(A.c, i, j, R, E) &&
+    if (in && setup_ray(A.c, i, j, R, E) &&
         span_setup(R, E, A.t.base < A.max_level ? A.t.base : A.max_level, 2, w))
       walk_span<OP>(A.t, R, E, A.max_level, A.field, A.wfield, A.los, Pf);
+    float* q = full_part + w * 256 + lane;
+    q[0] = Pf.s0;
+    q[64] = Pf.c0;
+    q[128] = Pf.s1;
+    q[192] = Pf.c1;
+  }
+  Partial Pl;
+  partial_init<OP>(Pl);
+  {
+    Ray R;
+    Entry E;
+    if (in && setup_ray(A.c, i, j, R, E) && span_setup(R, E, A.t.base < L ? A.t.base : L, 2, w))
+      walk_span<OP>(A.t, R, E, L, A.field, A.wfield, A.los, Pl);
   }
   if (w == 1) {
     float* q = part + lane;
@@ -528,10 +541,6 @@ __global__ __launch_bounds__(128) void k_render_tiles(
     q[64] = Pl.c0;
     q[128] = Pl.s1;
     q[192] = Pl.c1;
-    q[256] = Pf.s0;
-    q[320] = Pf.c0;
-    q[384] = Pf.s1;
-    q[448] = Pf.c1;
   }
   __syncthreads();
   if (w == 1 || !in) return;
@@ -540,7 +549,10 @@ __global__ __launch_bounds__(128) void k_render_tiles(
   float o = 0.f, x = 0.f;
   partial_finish<OP>(Pl, o, x);
   if (aud) {
-    partial_merge<OP>(Pf, Partial{q[256], q[320], q[384], q[448]});
+    const float* f0 = full_part + lane;
+    const float* f1 = full_part + 256 + lane;
+    Partial Pf{f0[0], f0[64], f0[128], f0[192]};
+    partial_merge<OP>(Pf, Partial{f1[0], f1[64], f1[128], f1[192]});
     float of = 0.f, xf = 0.f;
     partial_finish<OP>(Pf, of, xf);
     const float d = fabsf(o - of);
