@@ -331,9 +331,11 @@ amr_status amr_lod_adam_step(amr_lod_model* m, float lr, amr_stream s);
 amr_status amr_lod_labels(const float* const* imgs, int32_t W, int32_t H, float tol, int8_t* labels, amr_stream s);
 
 /* Render with the learned per-tile levels (tiles at or above the camera's
- * max_level render exactly like amr_render; audited tiles below it are
- * rendered at both levels in the same wave).  workspace: device, 256-byte
- * aligned, at least amr_lod_workspace_bytes(W, H).  tile_levels (device int8
+ * max_level render exactly like amr_render; audited tiles below it are also
+ * rendered at full depth, in other blocks of the same launch, and a second
+ * launch repairs their pixels).  workspace: device, 256-byte aligned, at
+ * least amr_lod_workspace_bytes(W, H) (features and plan of the tiles, and
+ * two fp32 W x H planes for the audit).  tile_levels (device int8
  * [tiles] or NULL) receives the levels used; forced_levels (device int8
  * [tiles] or NULL) replaces the network's choice (tests of the audit).
  * stats: device int64[8] overwritten with tiles, fallbacks, audited tiles,

@@ -485,23 +485,20 @@ __global__ void k_zero_stats(unsigned long long* s) {
 // 8 x 8 packets (inside one 16 x 16 tile), tree truncated at the tile's
 // level, every ray walked in two spans by the block's two waves exactly as
 // the default plain render does (a tile at full depth is bit-identical to
-// it).  Audited tiles below full depth are also rendered at full depth in the
-// same block; a pixel off by more than tol keeps the full-depth value and is
-// counted.  The two walks of an audited block run one after the other and
-// the first one's partial sums wait in LDS, so that the kernel holds the
-// registers of one walk only.
+// it).  The grid covers the packets twice.  The first half, dispatched
+// first, walks the packets of audited tiles (tiles below full depth picked
+// for checking) at full depth into the full-depth planes; the second half
+// walks every packet at its tile's level into out.  So the two walks of an
+// audited packet run in different blocks at the same time, and an audited
+// packet full of long rays does not double the image's tail.
 template <int OP>
-__global__ __launch_bounds__(128) void k_render_tiles(
-    RenderArgs A, const int8_t* __restrict__ level, const uint8_t* __restrict__ audit, int tiles_x, float tol,
-    unsigned long long* stats) {
-  __shared__ float full_part[2 * 4 * 64];  // full-depth partials of both span waves
-  __shared__ float part[4 * 64];           // level-L partials of span wave 1
+__global__ __launch_bounds__(128) void k_render_tiles(RenderArgs A, const int8_t* __restrict__ level,
+                                                      const uint8_t* __restrict__ audit, int tiles_x,
+                                                      float* __restrict__ full_out, float* __restrict__ full_aux) {
+  __shared__ float part[4 * 64];
   const int lane = threadIdx.x & 63, w = (int)(threadIdx.x >> 6);
-  // The grid covers the packets twice: audited packets are walked by the
-  // first half, which is dispatched first, so their doubled work starts early
-  // instead of landing in the tail; every other packet by the second half.
-  // Each half takes the packet rows from the middle of the image out, as the
-  // default plain render does.
+  // each half takes the packet rows from the middle of the image out, as the
+  // default plain render does
   const int np = A.packets_x * A.packets_y;
   const bool audit_half = (int)blockIdx.x < np;
   const int packet = center_out(audit_half ? (int)blockIdx.x : (int)blockIdx.x - np, A.packets_x, A.packets_y);
@@ -511,61 +508,62 @@ __global__ __launch_bounds__(128) void k_render_tiles(
   // a packet lies inside one tile: its level and audit flag are block-uniform
   const int t = (ty * 8 / kTile) * tiles_x + (tx * 8 / kTile);
   const int L = level[t];
-  const bool aud = audit[t] && L < A.max_level;
-  if (aud != audit_half) return;  // whole block
-  if (aud) {
-    Partial Pf;
-    partial_init<OP>(Pf);
-    Ray R;
-    Entry E;
-    if (in && setup_ray(A.c, i, j, R, E) &&
-        span_setup(R, E, A.t.base < A.max_level ? A.t.base : A.max_level, 2, w))
-      walk_span<OP>(A.t, R, E, A.max_level, A.field, A.wfield, A.los, Pf);
-    float* q = full_part + w * 256 + lane;
-    q[0] = Pf.s0;
-    q[64] = Pf.c0;
-    q[128] = Pf.s1;
-    q[192] = Pf.c1;
-  }
-  Partial Pl;
-  partial_init<OP>(Pl);
-  {
-    Ray R;
-    Entry E;
-    if (in && setup_ray(A.c, i, j, R, E) && span_setup(R, E, A.t.base < L ? A.t.base : L, 2, w))
-      walk_span<OP>(A.t, R, E, L, A.field, A.wfield, A.los, Pl);
-  }
+  if (audit_half && !(audit[t] && L < A.max_level)) return;  // whole block
+  const int lw = audit_half ? A.max_level : L;
+  Partial P;
+  partial_init<OP>(P);
+  Ray R;
+  Entry E;
+  if (in && setup_ray(A.c, i, j, R, E) && span_setup(R, E, A.t.base < lw ? A.t.base : lw, 2, w))
+    walk_span<OP>(A.t, R, E, lw, A.field, A.wfield, A.los, P);
   if (w == 1) {
     float* q = part + lane;
-    q[0] = Pl.s0;
-    q[64] = Pl.c0;
-    q[128] = Pl.s1;
-    q[192] = Pl.c1;
+    q[0] = P.s0;
+    q[64] = P.c0;
+    q[128] = P.s1;
+    q[192] = P.c1;
   }
   __syncthreads();
   if (w == 1 || !in) return;
   const float* q = part + lane;
-  partial_merge<OP>(Pl, Partial{q[0], q[64], q[128], q[192]});
+  partial_merge<OP>(P, Partial{q[0], q[64], q[128], q[192]});
   float o = 0.f, x = 0.f;
-  partial_finish<OP>(Pl, o, x);
-  if (aud) {
-    const float* f0 = full_part + lane;
-    const float* f1 = full_part + 256 + lane;
-    Partial Pf{f0[0], f0[64], f0[128], f0[192]};
-    partial_merge<OP>(Pf, Partial{f1[0], f1[64], f1[128], f1[192]});
-    float of = 0.f, xf = 0.f;
-    partial_finish<OP>(Pf, of, xf);
-    const float d = fabsf(o - of);
-    const bool bad = of != 0.f ? d > tol * fabsf(of) : d != 0.f;
-    if (bad) {
-      o = of;
-      x = xf;
-      atomicAdd(&stats[3], 1ull);
-    }
-  }
+  partial_finish<OP>(P, o, x);
   const int64_t pix = (int64_t)j * A.c.W + i;
-  A.out[pix] = o;
-  if (OP == kOpWMean && A.aux) A.aux[pix] = x;
+  if (audit_half) {
+    full_out[pix] = o;
+    if (OP == kOpWMean) full_aux[pix] = x;
+  } else {
+    A.out[pix] = o;
+    if (OP == kOpWMean && A.aux) A.aux[pix] = x;
+  }
+}
+
+// Audit of the tiles rendered below full depth: a pixel of an audited tile
+// off by more than tol (relative to the full-depth value; any difference
+// when that is 0) takes the full-depth value and is counted.  One wave per
+// 8 x 8 packet; packets of other tiles return at once.
+template <int OP>
+__global__ __launch_bounds__(64) void k_audit_repair(RenderArgs A, const int8_t* __restrict__ level,
+                                                     const uint8_t* __restrict__ audit, int tiles_x, float tol,
+                                                     const float* __restrict__ full_out,
+                                                     const float* __restrict__ full_aux, unsigned long long* stats) {
+  const int lane = threadIdx.x & 63;
+  const int packet = (int)blockIdx.x;
+  const int ty = packet / A.packets_x, tx = packet - ty * A.packets_x;
+  const int i = tx * 8 + (lane & 7), j = ty * 8 + (lane >> 3);
+  if (ty >= A.packets_y || i >= A.c.W || j >= A.c.H) return;
+  const int t = (ty * 8 / kTile) * tiles_x + (tx * 8 / kTile);
+  if (!(audit[t] && level[t] < A.max_level)) return;
+  const int64_t pix = (int64_t)j * A.c.W + i;
+  const float o = A.out[pix], of = full_out[pix];
+  const float d = fabsf(o - of);
+  const bool bad = of != 0.f ? d > tol * fabsf(of) : d != 0.f;
+  if (bad) {
+    A.out[pix] = of;
+    if (OP == kOpWMean && A.aux) A.aux[pix] = full_aux[pix];
+    atomicAdd(&stats[3], 1ull);
+  }
 }
 
 }  // namespace lod
@@ -854,10 +852,21 @@ amr_status amr_lod_labels(const float* const* imgs, int32_t W, int32_t H, float 
   return e == hipSuccess ? AMR_OK : fail(AMR_EHIP, hipGetErrorString(e));
 }
 
-int64_t amr_lod_workspace_bytes(int32_t W, int32_t H) {
+// Workspace layout (256-byte aligned parts): 256 reserved bytes, features
+// (bf16 [tiles][kIn]), logits (fp32 [tiles][kOut]), tile levels and audit
+// flags (int8 [tiles] each), then the two full-depth planes of the audit
+// (fp32 [H][W] each: value, and weight for WMEAN).
+namespace {
+int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
+int64_t ws_planes_offset(int32_t W, int32_t H) {
   const int64_t nt = amr_lod_tiles(W, H);
   const int64_t n16 = (nt + 15) / 16 * 16;
-  return 256 + n16 * kIn * 2 + n16 * kOut * 4 + 2 * n16 + 64;
+  return align256(256 + n16 * kIn * 2 + n16 * kOut * 4 + 2 * n16 + 64);
+}
+}  // namespace
+
+int64_t amr_lod_workspace_bytes(int32_t W, int32_t H) {
+  return ws_planes_offset(W, H) + 2 * align256((int64_t)W * H * 4);
 }
 
 amr_status amr_render_lod(const amr_tree* t, const amr_camera* cam, amr_op op, const amr_lod_model* m,
@@ -904,12 +913,22 @@ amr_status amr_render_lod(const amr_tree* t, const amr_camera* cam, amr_op op, c
   a.packets_x = (cam->W + 7) / 8;
   a.packets_y = (cam->H + 7) / 8;
   const unsigned np = (unsigned)(a.packets_x * a.packets_y);
-  if (op == AMR_SUM)
-    hipLaunchKernelGGL(k_render_tiles<kOpSum>, dim3(2 * np), dim3(128), 0, hs, a, lev, aud, tx, c.rel_tol, st);
-  else if (op == AMR_MAX)
-    hipLaunchKernelGGL(k_render_tiles<kOpMax>, dim3(2 * np), dim3(128), 0, hs, a, lev, aud, tx, c.rel_tol, st);
-  else
-    hipLaunchKernelGGL(k_render_tiles<kOpWMean>, dim3(2 * np), dim3(128), 0, hs, a, lev, aud, tx, c.rel_tol, st);
+  float* full_out = (float*)(w + ws_planes_offset(cam->W, cam->H));
+  float* full_aux = (float*)((char*)full_out + align256((int64_t)cam->W * cam->H * 4));
+  if (op == AMR_SUM) {
+    hipLaunchKernelGGL(k_render_tiles<kOpSum>, dim3(2 * np), dim3(128), 0, hs, a, lev, aud, tx, full_out, full_aux);
+    hipLaunchKernelGGL(k_audit_repair<kOpSum>, dim3(np), dim3(64), 0, hs, a, lev, aud, tx, c.rel_tol, full_out,
+                       full_aux, st);
+  } else if (op == AMR_MAX) {
+    hipLaunchKernelGGL(k_render_tiles<kOpMax>, dim3(2 * np), dim3(128), 0, hs, a, lev, aud, tx, full_out, full_aux);
+    hipLaunchKernelGGL(k_audit_repair<kOpMax>, dim3(np), dim3(64), 0, hs, a, lev, aud, tx, c.rel_tol, full_out,
+                       full_aux, st);
+  } else {
+    hipLaunchKernelGGL(k_render_tiles<kOpWMean>, dim3(2 * np), dim3(128), 0, hs, a, lev, aud, tx, full_out,
+                       full_aux);
+    hipLaunchKernelGGL(k_audit_repair<kOpWMean>, dim3(np), dim3(64), 0, hs, a, lev, aud, tx, c.rel_tol, full_out,
+                       full_aux, st);
+  }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? AMR_OK : fail(AMR_EHIP, hipGetErrorString(e));
 }
