@@ -116,7 +116,7 @@ __global__ __launch_bounds__(64 * K) void k_batch_grid(const BatchImage* __restr
   Ray R;
   Entry E;
   if (in && setup_ray(I.c, i, j, R, E) && span_setup(R, E, b0, K, w))
-    walk_span<OP>(I.t, R, E, I.max_level, I.field, I.wfield, I.los, P);
+    walk_span<OP, K == 1>(I.t, R, E, I.max_level, I.field, I.wfield, I.los, P);
   if (K > 1) {
     if (w > 0) {
       float* u = part + (w - 1) * 4 * 64 + lane;

@@ -421,10 +421,22 @@ AMR_HD int32_t walk(const TreeView& T, const Ray& R, Entry& E, int max_level, Vi
   return nseg;
 }
 
+// Three-input bitwise operations.  On gfx950 the three-input logic
+// instruction issues at the full rate of a two-input one, where the
+// compiler's own choices (or3, bfi) issue at half rate.
+#if defined(__HIP_DEVICE_COMPILE__)
+__device__ inline uint32_t or3(uint32_t a, uint32_t b, uint32_t c) { return __builtin_amdgcn_bitop3_b32(a, b, c, 0xFE); }
+// bits of a where m is set, of b elsewhere
+__device__ inline uint32_t bitsel(uint32_t m, uint32_t a, uint32_t b) { return __builtin_amdgcn_bitop3_b32(m, a, b, 0xCA); }
+#else
+inline uint32_t or3(uint32_t a, uint32_t b, uint32_t c) { return a | b | c; }
+inline uint32_t bitsel(uint32_t m, uint32_t a, uint32_t b) { return (m & a) | (~m & b); }
+#endif
+
 // Octant (bit 0 = x, bit 1 = y, bit 2 = z) of the coordinates' bits at
 // position s, s >= 2.
 AMR_HD uint32_t octant_bits(int32_t x, int32_t y, int32_t z, int s) {
-  return (((uint32_t)x >> s) & 1u) | (((uint32_t)y >> (s - 1)) & 2u) | (((uint32_t)z >> (s - 2)) & 4u);
+  return or3(((uint32_t)x >> s) & 1u, ((uint32_t)y >> (s - 1)) & 2u, ((uint32_t)z >> (s - 2)) & 4u);
 }
 
 // Morton-code step of one complete-level cell along axis k (0, 1, 2) by +1
@@ -433,7 +445,7 @@ AMR_HD uint32_t octant_bits(int32_t x, int32_t y, int32_t z, int s) {
 // included) into the axis' own bits.
 AMR_HD uint32_t morton_inc(uint32_t m, int k, bool c) {
   const uint32_t mk = 0x09249249u << k;
-  return (((m | ~mk) + (c ? 1u : 0u)) & mk) | (m & ~mk);
+  return bitsel(mk, (m | ~mk) + (c ? 1u : 0u), m);
 }
 
 // The same walk as walk<false> (identical cells, chords and order), with
@@ -450,7 +462,10 @@ AMR_HD uint32_t morton_inc(uint32_t m, int k, bool c) {
 //    current level are left stale and refined when a deeper cell needs
 //    them);
 //  - visitors that do not use chord lengths skip their arithmetic.
-template <class Vis>
+// kWholeBox: the ray's stop planes are the box faces (R.stop = 2^28 on every
+// axis, as setup_ray leaves them), which makes the end test one comparison.
+// On return E is no longer the entry state of any cell.
+template <class Vis, bool kWholeBox = false>
 AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_level, Vis& vis) {
   const int b0 = T.base < max_level ? T.base : max_level;
   const int sb = kFix - b0;
@@ -472,8 +487,8 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
   uint32_t mb = morton3((uint32_t)(E.p[0] >> sb), (uint32_t)(E.p[1] >> sb), (uint32_t)(E.p[2] >> sb));
   const int32_t offb = T.off[b0];  // first cell of the complete base level
   int32_t pfc = -1;  // first-child index of the current cell's parent (-1: none cached)
-  int plv = -1;      // level of that parent
-  int jr = -1;       // restart level
+  int plv = -2;      // level of that parent (-2: none, never equal to jr)
+  int jr = -1;       // restart level (>= -1)
   int32_t nseg = 0;
   // per-axis copies of E.exact (lane masks, not integer bits, so that no
   // select is spent packing and unpacking them on every cell)
@@ -481,7 +496,7 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
   for (;;) {
     int lvl;
     int32_t node;
-    if (jr >= 0 && jr == plv) {
+    if (jr == plv) {
       lvl = jr + 1;  // sibling of the previous cell
       const int s = kFix - lvl;
       node = pfc + (int32_t)(octant_bits(E.p[0], E.p[1], E.p[2], s) ^ (fm & 7u));
@@ -489,7 +504,7 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
       lvl = b0;
       node = offb + (int32_t)((mb ^ fm) & mask3);
       pfc = -1;
-      plv = -1;
+      plv = -2;
     }
     AMR_CHECK_CELL(T, node);
     float v0;
@@ -525,7 +540,7 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
     }
     vis.fetch0(node, v0);
     const int s = kFix - lvl;
-    const int32_t low = (int32_t(1) << s) - 1;
+    const int32_t low = (int32_t)((uint32_t)(kOne - 1) >> lvl);  // (1 << s) - 1 by a (full-rate) right shift
     const int32_t X0 = (E.p[0] | low) + 1, X1 = (E.p[1] | low) + 1, X2 = (E.p[2] | low) + 1;
     const int32_t n0 = X0 - R.o[0], n1 = X1 - R.o[1], n2 = X2 - R.o[2];
     // exit parameters n_k / dv_k compared by cross-multiplication (the
@@ -545,14 +560,27 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
     float len = 0.0f;
     if (Vis::kNeedsLength) {
       const int64_t N = mul64(nb, E.da) - mul64(E.en, db);
-      if (lvl < kDeepLevel)
+      if (max_level < kDeepLevel || lvl < kDeepLevel)
         len = chord_f32(N, ulen, invb, E.inv_da);
       else
         len = (float)((double)N * R.ulen64 / ((double)E.da * (double)db));
     }
     vis.seg(node, lvl, len, E.p[0] >> s, E.p[1] >> s, E.p[2] >> s);
     ++nseg;
-    if ((t0 && X0 >= R.stop[0]) || (t1 && X1 >= R.stop[1]) || (t2 && X2 >= R.stop[2])) break;
+    // Next cell's coordinates: tied axes enter at their face exactly
+    // (X = (p | low) + 1); the others keep the current cell's prefix, their
+    // bits below this level left at one (stale from here: refinement
+    // recomputes them, for a fixed axis too, so only crossed axes are exact).
+    // An axis not crossed stays below its stop plane (no cell straddles one),
+    // so the ray ends when a coordinate reaches its stop plane.
+    E.p[0] = (X0 - 1) + (t0 ? 1 : 0);
+    E.p[1] = (X1 - 1) + (t1 ? 1 : 0);
+    E.p[2] = (X2 - 1) + (t2 ? 1 : 0);
+    if (kWholeBox) {
+      if ((uint32_t)(E.p[0] | E.p[1] | E.p[2]) >= (uint32_t)kOne) break;
+    } else {
+      if (E.p[0] >= R.stop[0] || E.p[1] >= R.stop[1] || E.p[2] >= R.stop[2]) break;
+    }
     // restart level and base-cell steps
     if (lvl == b0) {
       // a base-level cell (most cells of a typical tree): every tied axis
@@ -562,34 +590,27 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
       mb = morton_inc(mb, 1, t1);
       mb = morton_inc(mb, 2, t2);
     } else {
-      // a tied axis whose coordinate at this level ends in r one-bits
-      // carries r + 1 levels up
+      // a tied axis whose new coordinate at this level, c + 1, ends in r
+      // zero bits (the old c in r one-bits) carries r levels up
       const int span = lvl - b0;
       const int32_t bmask = (int32_t(1) << span) - 1;
       jr = lvl - 1;
       if (t0) {
-        const int32_t c = E.p[0] >> s;
-        jr = min(jr, lvl - 1 - (int)__builtin_ctz(~(uint32_t)c));
-        mb = morton_inc(mb, 0, ((c + 1) & bmask) == 0);
+        const int32_t c1 = E.p[0] >> s;
+        jr = min(jr, lvl - 1 - (int)__builtin_ctz((uint32_t)c1));
+        mb = morton_inc(mb, 0, (c1 & bmask) == 0);
       }
       if (t1) {
-        const int32_t c = E.p[1] >> s;
-        jr = min(jr, lvl - 1 - (int)__builtin_ctz(~(uint32_t)c));
-        mb = morton_inc(mb, 1, ((c + 1) & bmask) == 0);
+        const int32_t c1 = E.p[1] >> s;
+        jr = min(jr, lvl - 1 - (int)__builtin_ctz((uint32_t)c1));
+        mb = morton_inc(mb, 1, (c1 & bmask) == 0);
       }
       if (t2) {
-        const int32_t c = E.p[2] >> s;
-        jr = min(jr, lvl - 1 - (int)__builtin_ctz(~(uint32_t)c));
-        mb = morton_inc(mb, 2, ((c + 1) & bmask) == 0);
+        const int32_t c1 = E.p[2] >> s;
+        jr = min(jr, lvl - 1 - (int)__builtin_ctz((uint32_t)c1));
+        mb = morton_inc(mb, 2, (c1 & bmask) == 0);
       }
     }
-    // tied axes enter the next cell at their face exactly (X = (p | low) + 1);
-    // the others keep the current cell's prefix, their bits below this level
-    // left at one (stale from here: refinement recomputes them, for a fixed
-    // axis too, so only crossed axes are exact)
-    E.p[0] = (X0 - 1) + (t0 ? 1 : 0);
-    E.p[1] = (X1 - 1) + (t1 ? 1 : 0);
-    E.p[2] = (X2 - 1) + (t2 ? 1 : 0);
     ex0 = t0;
     ex1 = t1;
     ex2 = t2;
@@ -706,7 +727,7 @@ enum { kWalkBase = 0, kWalkStack = 1, kWalkFast = 2 };
 
 template <int MODE, class Vis, class Stack>
 AMR_HD int32_t walk_mode(const TreeView& T, const Ray& R, Entry& E, int max_level, Vis& v, Stack& S) {
-  if (MODE == kWalkFast) return walk_fast(T, R, E, max_level, v);
+  if (MODE == kWalkFast) return walk_fast<Vis, true>(T, R, E, max_level, v);
   return walk<MODE == kWalkStack>(T, R, E, max_level, v, S);
 }
 
@@ -884,18 +905,19 @@ AMR_HD void partial_init(Partial& P) {
   P.c0 = P.s1 = P.c1 = 0.0f;
 }
 
-template <int OP>
+// kWholeBox: the span is the whole ray (no stop plane inside the box).
+template <int OP, bool kWholeBox = false>
 AMR_HD void walk_span(const TreeView& T, const Ray& R, Entry& E, int max_level, int field, int wfield, int los,
                       Partial& P) {
   const int64_t nc = T.ncells;
   if (OP == kOpSum) {
     SumVis v{T.val + (int64_t)field * nc, field == 0};
-    walk_fast(T, R, E, max_level, v);
+    walk_fast<decltype(v), kWholeBox>(T, R, E, max_level, v);
     P.s0 = v.s;
     P.c0 = v.c;
   } else if (OP == kOpMax) {
     MaxVis v{T.val + (int64_t)field * nc, -INFINITY, field == 0};
-    walk_fast(T, R, E, max_level, v);
+    walk_fast<decltype(v), kWholeBox>(T, R, E, max_level, v);
     P.s0 = v.m;
   } else {
     WMeanVis v;
@@ -908,7 +930,7 @@ AMR_HD void walk_span(const TreeView& T, const Ray& R, Entry& E, int max_level, 
     const float n = sqrtf((float)(R.d64[0] * R.d64[0] + R.d64[1] * R.d64[1] + R.d64[2] * R.d64[2]));
     AMR_UNROLL
     for (int k = 0; k < 3; ++k) v.dh[k] = (float)R.d64[k] / n;
-    walk_fast(T, R, E, max_level, v);
+    walk_fast<decltype(v), kWholeBox>(T, R, E, max_level, v);
     P.s0 = v.sw;
     P.c0 = v.cw;
     P.s1 = v.sf;
