@@ -434,9 +434,10 @@ inline uint32_t bitsel(uint32_t m, uint32_t a, uint32_t b) { return (m & a) | (~
 #endif
 
 // Octant (bit 0 = x, bit 1 = y, bit 2 = z) of the coordinates' bits at
-// position s, s >= 2.
+// position s, s >= 2: each coordinate shifted so that its bit lands in its
+// octant position, then bit 0 taken from x, bit 1 from y, bit 2 from z.
 AMR_HD uint32_t octant_bits(int32_t x, int32_t y, int32_t z, int s) {
-  return or3(((uint32_t)x >> s) & 1u, ((uint32_t)y >> (s - 1)) & 2u, ((uint32_t)z >> (s - 2)) & 4u);
+  return bitsel(1u, (uint32_t)x >> s, bitsel(2u, (uint32_t)y >> (s - 1), (uint32_t)z >> (s - 2))) & 7u;
 }
 
 // Morton-code step of one complete-level cell along axis k (0, 1, 2) by +1
