@@ -302,7 +302,7 @@ struct FeatVis {
   __device__ void seg(int32_t, int, float l, int32_t, int32_t, int32_t) {
     col += x * l;
     len += l;
-    const float lg = log10f(fmaxf(x, 1e-30f));
+    const float lg = __log2f(fmaxf(x, 1e-30f));  // log2; scaled to log10 after the walk
     slg += l * lg;
     slg2 += l * lg * lg;
     int b = depth - kBin0;
@@ -339,6 +339,9 @@ __global__ __launch_bounds__(128) void k_features(TreeView T, CameraView C, int 
   const int b0 = T.base < lc ? T.base : lc;
   const bool hit = setup_ray(C, i, j, R, E);
   if (hit && span_setup(R, E, b0, 2, w)) nseg = walk_fast(T, R, E, lc, v);
+  constexpr float kLog10_2 = 0.30102999566398120f;
+  v.slg *= kLog10_2;
+  v.slg2 *= kLog10_2 * kLog10_2;
   if (w == 1) {
     part[0 * 64 + lane] = v.col;
     part[1 * 64 + lane] = v.len;
