@@ -161,3 +161,35 @@ def test_split_rays_disk_and_deep_levels():
                         fov_y=0.9, max_level=-1)
     R = SplitRenderer(L, 4)
     parity.compare_all(R, OT, cam, ops=("sum", "max"), trace_rays=np.arange(48 * 48)[::3], what="split deep")
+
+
+def test_whole_box_end_test_matches_per_axis_end_test():
+    """The fast walk ends a ray either by one comparison against the box
+    (rays that stop at the box: render_pixel) or by the per-axis stop planes
+    (spans: here one span per ray).  The two must give the same cells and
+    bit-identical results, degenerate rays included."""
+    rng = np.random.default_rng(77)
+    for seed in (21, 22):
+        L = amrgen.random_tree(seed, lmax=6, p_refine=0.45, nfields=4)
+        L.fields[1:] -= 5.0
+        T = amr.Tree(L, host_only=True)
+        E = emu.EmuTree(T)
+        for camd in rand_cams(rng, 4, W=33, H=29, inside=(seed % 2 == 1)) + degenerate_cams():
+            cam = amr.set_camera(camd, T)
+            for op, kw in ((0, {}), (1, {}), (2, dict(field=1, weight=0, los=True))):
+                a, ax, ca = E.render(cam, op, lca=2, **kw)
+                b, bx, cb, _ = E.render_split(cam, op, 1, **kw)
+                assert np.array_equal(a.view(np.int32), b.view(np.int32)), (seed, camd, op)
+                assert np.array_equal(ax.view(np.int32), bx.view(np.int32)), (seed, camd, op)
+                assert np.array_equal(ca, cb), (seed, camd, op)
+    # a disk refined to level 11: long rays, deep descents, sibling moves
+    L = amrgen.disk(seed=3, lmax=11, m_thr=2e-4)
+    T = amr.Tree(L, host_only=True)
+    E = emu.EmuTree(T)
+    rays = np.random.default_rng(5).choice(96 * 96, 1500, replace=False)
+    for camd in amrgen.disk_cameras(96, 96, max_level=11):
+        cam = amr.set_camera(camd, T)
+        a, _, ca = E.render(cam, 0, lca=2, rays=rays)
+        b, _, cb, _ = E.render_split(cam, 0, 1, rays=rays)
+        assert ca.sum() > 10 * len(rays)
+        assert np.array_equal(a.view(np.int32), b.view(np.int32)) and np.array_equal(ca, cb)
