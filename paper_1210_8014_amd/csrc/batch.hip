@@ -115,8 +115,13 @@ __global__ __launch_bounds__(64 * K) void k_batch_grid(const BatchImage* __restr
   partial_init<OP>(P);
   Ray R;
   Entry E;
-  if (in && setup_ray(I.c, i, j, R, E) && span_setup(R, E, b0, K, w))
-    walk_span<OP, K == 1>(I.t, R, E, I.max_level, I.field, I.wfield, I.los, P);
+  if (in && setup_ray(I.c, i, j, R, E) && span_setup(R, E, b0, K, w)) {
+    // the last span (the whole ray when K = 1) runs to the box: one-comparison end test
+    if (K == 1 || w == K - 1)
+      walk_span<OP, true>(I.t, R, E, I.max_level, I.field, I.wfield, I.los, P);
+    else
+      walk_span<OP>(I.t, R, E, I.max_level, I.field, I.wfield, I.los, P);
+  }
   if (K > 1) {
     if (w > 0) {
       float* u = part + (w - 1) * 4 * 64 + lane;

@@ -338,7 +338,8 @@ __global__ __launch_bounds__(128) void k_features(TreeView T, CameraView C, int 
   int32_t nseg = 0;
   const int b0 = T.base < lc ? T.base : lc;
   const bool hit = setup_ray(C, i, j, R, E);
-  if (hit && span_setup(R, E, b0, 2, w)) nseg = walk_fast(T, R, E, lc, v);
+  if (hit && span_setup(R, E, b0, 2, w))
+    nseg = w == 1 ? walk_fast<FeatVis, true>(T, R, E, lc, v) : walk_fast(T, R, E, lc, v);  // span 1 runs to the box
   constexpr float kLog10_2 = 0.30102999566398120f;
   v.slg *= kLog10_2;
   v.slg2 *= kLog10_2 * kLog10_2;
@@ -517,8 +518,12 @@ __global__ __launch_bounds__(128) void k_render_tiles(RenderArgs A, const int8_t
   partial_init<OP>(P);
   Ray R;
   Entry E;
-  if (in && setup_ray(A.c, i, j, R, E) && span_setup(R, E, A.t.base < lw ? A.t.base : lw, 2, w))
-    walk_span<OP>(A.t, R, E, lw, A.field, A.wfield, A.los, P);
+  if (in && setup_ray(A.c, i, j, R, E) && span_setup(R, E, A.t.base < lw ? A.t.base : lw, 2, w)) {
+    if (w == 1)  // the last span runs to the box
+      walk_span<OP, true>(A.t, R, E, lw, A.field, A.wfield, A.los, P);
+    else
+      walk_span<OP>(A.t, R, E, lw, A.field, A.wfield, A.los, P);
+  }
   if (w == 1) {
     float* q = part + lane;
     q[0] = P.s0;

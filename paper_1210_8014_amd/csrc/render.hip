@@ -82,8 +82,13 @@ __global__ __launch_bounds__(64 * K) void k_render_split(RenderArgs A) {
   partial_init<OP>(P);
   Ray R;
   Entry E;
-  if (in && setup_ray(A.c, i, j, R, E) && span_setup(R, E, b0, K, w))
-    walk_span<OP>(A.t, R, E, A.max_level, A.field, A.wfield, A.los, P);
+  if (in && setup_ray(A.c, i, j, R, E) && span_setup(R, E, b0, K, w)) {
+    // the last span always runs to the box (its one-comparison end test)
+    if (w == K - 1)
+      walk_span<OP, true>(A.t, R, E, A.max_level, A.field, A.wfield, A.los, P);
+    else
+      walk_span<OP>(A.t, R, E, A.max_level, A.field, A.wfield, A.los, P);
+  }
   if (w > 0) {
     float* q = part + (w - 1) * 4 * 64 + lane;
     q[0] = P.s0;
