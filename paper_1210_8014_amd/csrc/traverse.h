@@ -560,7 +560,8 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
     const float invb = p2 ? iv2 : (p1 ? iv1 : iv0);
     float len = 0.0f;
     if (Vis::kNeedsLength) {
-      const int64_t N = mul64(nb, E.da) - mul64(E.en, db);
+      // (the product of the negated entry numerator is the second one's addend)
+      const int64_t N = mul64(nb, E.da) + mul64(-E.en, db);
       if (max_level < kDeepLevel || lvl < kDeepLevel)
         len = chord_f32(N, ulen, invb, E.inv_da);
       else
