@@ -324,6 +324,9 @@ def main():
             "unit": "GB/s",
             "frac": kern[dom]["gbs"] / HBM_PEAK_GBS,
             "traffic": traffic,
+            # the algorithmic basis counts every segment's gather as HBM traffic; the
+            # measured DRAM rate (traffic / launch time) shows how much the caches absorb
+            "dram_GBs": (traffic / (kern[dom]["avg_ms"] * 1e-3) / 1e9) if traffic else None,
         },
         "cpu_baseline": cpu,
         "lod": lod_res,
