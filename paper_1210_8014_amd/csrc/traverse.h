@@ -149,6 +149,16 @@ AMR_HD void kahan_add(float& s, float& c, float x) {
   } while (0)
 #endif
 
+// A value the compiler may not rewrite in terms of what it was computed from
+// (a pure, instruction-free barrier: unlike AMR_KEEP_HERE it may be moved).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define AMR_OPAQUE(x) asm("" : "+v"(x))
+#else
+#define AMR_OPAQUE(x) \
+  do {                \
+  } while (0)
+#endif
+
 // A per-lane condition evaluated here, as a lane mask in scalar registers.
 // Without it the compiler re-evaluates a comparison at each later use and
 // keeps its (wide) operands live until then.  Emits no instruction.
@@ -475,6 +485,11 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
   // (n_j * 0 < n_k * d_j for every moving axis j, as every n > 0), and the
   // refinement of its coordinate bits sees d = 0 as it should.
   const int32_t dv0 = R.d[0], dv1 = R.d[1], dv2 = R.d[2];
+  // 1 - o: the exit numerator X - o of a cell is (p | low) + co, one add
+  int32_t co0 = 1 - R.o[0], co1 = 1 - R.o[1], co2 = 1 - R.o[2];
+  AMR_OPAQUE(co0);
+  AMR_OPAQUE(co1);
+  AMR_OPAQUE(co2);
   const float ulen = R.ulen;
   const float iv0 = R.inv_d[0], iv1 = R.inv_d[1], iv2 = R.inv_d[2];
   const int32_t f0 = R.flip[0], f1 = R.flip[1], f2 = R.flip[2];
@@ -528,11 +543,12 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
         const int32_t known = ~((int32_t(1) << (kFix - E.lam)) - 1);
         const bool exk[3] = {ex0, ex1, ex2};
         const int32_t dvk[3] = {dv0, dv1, dv2};
+        const int32_t cok[3] = {co0, co1, co2};
         AMR_UNROLL
         for (int k = 0; k < 3; ++k) {
           if (exk[k]) continue;
           const int32_t M = (E.p[k] & known) + (int32_t(1) << s);
-          E.p[k] = mul64(en, dvk[k]) >= mul64(M - R.o[k], E.da) ? M : (E.p[k] & known);
+          E.p[k] = mul64(en, dvk[k]) >= mul64(M + cok[k] - 1, E.da) ? M : (E.p[k] & known);
         }
         E.lam = lvl;
       }
@@ -542,8 +558,9 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
     vis.fetch0(node, v0);
     const int s = kFix - lvl;
     const int32_t low = (int32_t)((uint32_t)(kOne - 1) >> lvl);  // (1 << s) - 1 by a (full-rate) right shift
-    const int32_t X0 = (E.p[0] | low) + 1, X1 = (E.p[1] | low) + 1, X2 = (E.p[2] | low) + 1;
-    const int32_t n0 = X0 - R.o[0], n1 = X1 - R.o[1], n2 = X2 - R.o[2];
+    // last coordinate inside the cell (the exit plane is h + 1) and exit numerators
+    const int32_t h0 = E.p[0] | low, h1 = E.p[1] | low, h2 = E.p[2] | low;
+    const int32_t n0 = h0 + co0, n1 = h1 + co1, n2 = h2 + co2;
     // exit parameters n_k / dv_k compared by cross-multiplication (the
     // products of 31-bit factors compare directly, no difference needed)
     const int64_t P0 = mul64(n0, dv1), P1 = mul64(n1, dv0);
@@ -575,9 +592,9 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
     // recomputes them, for a fixed axis too, so only crossed axes are exact).
     // An axis not crossed stays below its stop plane (no cell straddles one),
     // so the ray ends when a coordinate reaches its stop plane.
-    E.p[0] = (X0 - 1) + (t0 ? 1 : 0);
-    E.p[1] = (X1 - 1) + (t1 ? 1 : 0);
-    E.p[2] = (X2 - 1) + (t2 ? 1 : 0);
+    E.p[0] = h0 + (t0 ? 1 : 0);
+    E.p[1] = h1 + (t1 ? 1 : 0);
+    E.p[2] = h2 + (t2 ? 1 : 0);
     if (kWholeBox) {
       if ((uint32_t)(E.p[0] | E.p[1] | E.p[2]) >= (uint32_t)kOne) break;
     } else {
