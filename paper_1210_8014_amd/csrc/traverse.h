@@ -703,7 +703,9 @@ struct WMeanVis {
   AMR_HD void seg(int32_t, int, float len, int32_t, int32_t, int32_t) {
     const float wl = xw * len;
     float f = x0;
-    if (los) f = x0 * dh[0] + x1 * dh[1] + x2 * dh[2];
+    // line-of-sight velocity v . d^, as fused multiply-adds (correctly
+    // rounded on host and device alike)
+    if (los) f = fmaf(x2, dh[2], fmaf(x1, dh[1], x0 * dh[0]));
     kahan_add(sw, cw, wl);
     kahan_add(sf, cf, wl * f);
   }
