@@ -419,8 +419,7 @@ def bench_batch(args):
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": ("k_batch_grid<0, %d>" % (2 if "split2" in amr.batch_configs()[best] else 1))
-                      if "grid" in amr.batch_configs()[best] else "k_batch<0, ...>",
+            "kernel": batch_kernel_name(amr.batch_configs()[best], "sum"),
             "achieved": alg / tb / 1e9,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
