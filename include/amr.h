@@ -261,7 +261,7 @@ amr_status amr_set_default_variant(amr_tree* t, amr_op op, int32_t v);
  * camera-wide level from the pixel size; here a network predicts, for each
  * 16 x 16 pixel tile, the shallowest level L in 1..16 whose render stays
  * within rel_tol of the full-depth render.
- *   coarse_level  level at which the 16 probe rays per tile are walked (7)
+ *   coarse_level  level at which the 16 probe rays per tile are walked (4)
  *   quantile      level = first class whose cumulative probability >= q
  *   conf_thresh   tiles whose top class probability is below it render at
  *                 full depth (>= 1 forces full depth everywhere)
@@ -333,9 +333,10 @@ amr_status amr_lod_labels(const float* const* imgs, int32_t W, int32_t H, float 
 /* Render with the learned per-tile levels (tiles at or above the camera's
  * max_level render exactly like amr_render; audited tiles below it are also
  * rendered at full depth, in other blocks of the same launch, and a second
- * launch repairs their pixels).  workspace: device, 256-byte aligned, at
- * least amr_lod_workspace_bytes(W, H) (features and plan of the tiles, and
- * two fp32 W x H planes for the audit).  tile_levels (device int8
+ * launch repairs their pixels).  Four launches: features, network and plan
+ * (one kernel), tile render, repair.  workspace: device, 256-byte aligned, at
+ * least amr_lod_workspace_bytes(W, H) (features, logits and plan of the
+ * tiles, 4 KiB of counters, and two fp32 W x H planes for the audit).  tile_levels (device int8
  * [tiles] or NULL) receives the levels used; forced_levels (device int8
  * [tiles] or NULL) replaces the network's choice (tests of the audit).
  * stats: device int64[8] overwritten with tiles, fallbacks, audited tiles,

@@ -48,7 +48,7 @@ struct RenderArgs {
 // ...): the rays that cross the most cells usually look through the middle
 // of the image, and started first their walks overlap the rest of the image
 // instead of finishing alone at its end.
-AMR_HD inline int center_out(int b, int px, int py) {
+AMR_HD int center_out(int b, int px, int py) {
   const int k = b / px, x = b - k * px;
   const int row = py / 2 + ((k & 1) ? -((k + 1) >> 1) : (k >> 1));
   return row * px + x;

@@ -35,6 +35,13 @@ namespace lod {
 constexpr int kIn = 32, kHid = 64, kOut = 16, kCls = 16, kLv0 = 1, kTile = 16;
 // subtree-depth histogram of the probe features: levels 7..16
 constexpr int kBins = 10, kBin0 = 7;
+// packets checked by one wave of the audit repair launch
+constexpr int kRepairPackets = 16;
+// The plan's counters (tiles, fallbacks, audited, level sum) are added into
+// kStatSlots copies on separate 128-byte lines, picked by block index, so
+// that the blocks' atomics do not all wait on one address; the repair launch
+// folds the copies into the caller's statistics.
+constexpr int kStatSlots = 32, kSlotU64 = 16;
 // parameter offsets (floats) in the fp32 master buffer; the bf16 weight
 // buffer uses the same offsets
 constexpr int oW1 = 0, oB1 = oW1 + kIn * kHid, oW2 = oB1 + kHid, oB2 = oW2 + kHid * kHid, oW3 = oB2 + kHid,
@@ -101,31 +108,106 @@ __device__ inline f32x4 block_lds_x_wt(const uint16_t* A, int lda, const uint16_
   return acc;
 }
 
+// ------------------------------------------------------------------ plan
+// SplitMix64 finaliser (Steele, Lea and Flood, 2014), high 32 bits: the
+// audited-tile selection.
+__device__ inline uint32_t hash32(uint64_t x) {
+  x += 0x9e3779b97f4a7c15ULL;
+  x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  x = (x ^ (x >> 27)) * 0x94d049bb133111ebULL;
+  return (uint32_t)((x ^ (x >> 31)) >> 32);
+}
+
+struct PlanArgs {
+  float q, conf_thresh;
+  int full_level;
+  float audit_frac;
+  uint64_t audit_seed;
+  const int8_t* forced;            // optional per-tile levels that replace the prediction
+  int8_t* level;                   // out: per-tile level
+  uint8_t* audit;                  // out: per-tile audit flag
+  unsigned long long* slots;       // kStatSlots x {tiles, fallbacks, audited, level sum}, kSlotU64 apart
+};
+
+// Level of one tile from its kCls class logits, computed by the 16 lanes of
+// a lane group, lane r holding class r (zc): the first class whose
+// cumulative softmax probability reaches q, or full depth when the top
+// probability is below the confidence threshold.  Max, sum and the
+// cumulative sum are lane-group reductions and a scan (their rounding order
+// is that of the shuffles); every lane of the group returns the same level.
+__device__ inline int plan_group(float zc, int r, int64_t t, const PlanArgs& A, bool& fallback) {
+  static_assert(kCls == 16, "one class per lane of a 16-lane group");
+  float m = zc;
+  for (int off = 8; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 16));
+  const float e = expf(zc - m);
+  float sum = e;
+  for (int off = 8; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 16);
+  const float pc = e / sum;
+  float pmax = pc;
+  for (int off = 8; off > 0; off >>= 1) pmax = fmaxf(pmax, __shfl_xor(pmax, off, 16));
+  float cdf = pc;  // inclusive scan over the classes
+  for (int d = 1; d < 16; d <<= 1) {
+    const float o = __shfl_up(cdf, d, 16);
+    if (r >= d) cdf += o;
+  }
+  const unsigned long long hit = __ballot(cdf >= A.q);
+  const unsigned grp = (unsigned)(hit >> (threadIdx.x & 48)) & 0xFFFFu;  // this lane group's classes
+  int L = kLv0 + (grp ? __ffs(grp) - 1 : kCls - 1);
+  fallback = !(pmax >= A.conf_thresh) || A.conf_thresh >= 1.f;
+  if (fallback) L = A.full_level;
+  if (A.forced) L = A.forced[t];
+  if (L > A.full_level) L = A.full_level;
+  if (L < 0) L = 0;
+  return L;
+}
+
+__device__ inline bool audit_draw(int64_t t, const PlanArgs& A) {
+  return A.audit_frac >= 1.f || (double)hash32(A.audit_seed * 0x100000001b3ULL + (uint64_t)t) <
+                                    (double)A.audit_frac * 4294967296.0;
+}
+
 // --------------------------------------------------------------- forward
-// One wave (block of 64) per 16 samples.  X: [n][32] bf16.  Wb: bf16
-// weights, P: fp32 parameters (biases).  logits: [n][16] fp32.  acts
-// (optional): [3][n][64] bf16 post-ReLU activations, for the backward pass.
-__global__ __launch_bounds__(64) void k_fwd(const uint16_t* __restrict__ X, int64_t n, const uint16_t* __restrict__ Wb,
-                                            const float* __restrict__ P, float* __restrict__ logits,
-                                            uint16_t* __restrict__ acts) {
-  __shared__ uint16_t hA[16 * kHid];
-  __shared__ uint16_t hB[16 * kHid];
-  const int lane = threadIdx.x, r = lane & 15, g = lane >> 4;
-  const int64_t r0 = (int64_t)blockIdx.x * 16;
-  // stage the input rows
+// One block = kFwdWaves waves, each computing 16 samples through the four
+// layers; the weights and biases are staged in LDS once per block, so every
+// layer reads its operands from LDS (no chain of dependent global loads).
+// X: [n][32] bf16.  Wb: bf16 weights, P: fp32 parameters (biases).
+// logits: [n][16] fp32.  acts (optional): [3][n][64] bf16 post-ReLU
+// activations, for the backward pass.  kPlan: the wave then plans its 16
+// tiles from the logits in its registers (plan_group, one 16-lane group per
+// tile) and adds its counts to one of the statistics slots.
+constexpr int kFwdWaves = 4;
+template <bool kPlan>
+__global__ __launch_bounds__(64 * kFwdWaves) void k_fwd(const uint16_t* __restrict__ X, int64_t n,
+                                                        const uint16_t* __restrict__ Wb,
+                                                        const float* __restrict__ P, float* __restrict__ logits,
+                                                        uint16_t* __restrict__ acts, PlanArgs plan) {
+  static_assert(kParams % 8 == 0, "weights are staged in 16-byte pieces");
+  __shared__ uint4 sW4[kParams / 8];              // bf16 weights (the bias slots are not read)
+  __shared__ float sBias[3 * kHid + kOut];        // b1 | b2 | b3 | b4
+  __shared__ uint16_t act[kFwdWaves][2][16 * kHid];
+  const int lane = threadIdx.x & 63, wv = (int)(threadIdx.x >> 6), r = lane & 15, g = lane >> 4;
+  for (int e = (int)threadIdx.x; e < kParams / 8; e += 64 * kFwdWaves) sW4[e] = ((const uint4*)Wb)[e];
+  for (int e = (int)threadIdx.x; e < 3 * kHid + kOut; e += 64 * kFwdWaves)
+    sBias[e] = P[e < kHid ? oB1 + e : e < 2 * kHid ? oB2 + (e - kHid) : e < 3 * kHid ? oB3 + (e - 2 * kHid)
+                                                                                    : oB4 + (e - 3 * kHid)];
+  const uint16_t* sW = (const uint16_t*)sW4;
+  const int64_t r0 = ((int64_t)blockIdx.x * kFwdWaves + wv) * 16;
+  uint16_t* in = act[wv][0];
+  uint16_t* out = act[wv][1];
+  // stage the wave's input rows
   for (int e = lane; e < 16 * kIn; e += 64) {
     const int row = e / kIn, k = e % kIn;
-    hA[row * kHid + k] = r0 + row < n ? X[(r0 + row) * kIn + k] : (uint16_t)0;
+    in[row * kHid + k] = r0 + row < n ? X[(r0 + row) * kIn + k] : (uint16_t)0;
   }
   __syncthreads();
-  const uint16_t* in = hA;
-  uint16_t* out = hB;
-  const int wofs[3] = {oW1, oW2, oW3}, bofs[3] = {oB1, oB2, oB3}, kin[3] = {kIn, kHid, kHid};
+#pragma unroll 1
   for (int L = 0; L < 3; ++L) {
+    const int wofs = L == 0 ? oW1 : L == 1 ? oW2 : oW3, kin = L == 0 ? kIn : kHid;
+#pragma unroll 1
     for (int cb = 0; cb < kHid / 16; ++cb) {
-      f32x4 acc = block_lds_x_w(in, kHid, Wb + wofs[L], kHid, cb * 16, kin[L] / 32, kin[L]);
+      f32x4 acc = block_lds_x_w(in, kHid, sW + wofs, kHid, cb * 16, kin / 32, kin);
       const int col = cb * 16 + r;
-      const float bias = P[bofs[L] + col];
+      const float bias = sBias[L * kHid + col];
       for (int i = 0; i < 4; ++i) {
         const int row = g * 4 + i;
         float v = acc[i] + bias;
@@ -136,14 +218,45 @@ __global__ __launch_bounds__(64) void k_fwd(const uint16_t* __restrict__ X, int6
       }
     }
     __syncthreads();
-    const uint16_t* t = in;
+    uint16_t* t = in;
     in = out;
-    out = const_cast<uint16_t*>(t);
+    out = t;
   }
-  f32x4 acc = block_lds_x_w(in, kHid, Wb + oW4, kOut, 0, kHid / 32, kHid);
+  f32x4 acc = block_lds_x_w(in, kHid, sW + oW4, kOut, 0, kHid / 32, kHid);
+  unsigned long long nv = 0, nf = 0, na = 0, lsum = 0;  // counted by lane r = 0 of each group
   for (int i = 0; i < 4; ++i) {
-    const int row = g * 4 + i;
-    if (r0 + row < n) logits[(r0 + row) * kOut + r] = acc[i] + P[oB4 + r];
+    const int64_t row = r0 + g * 4 + i;
+    const float z = acc[i] + sBias[3 * kHid + r];
+    if (row < n) logits[row * kOut + r] = z;
+    if (kPlan) {
+      // lane group g holds the 16 class logits of row g * 4 + i, lane r class r
+      bool fb;
+      const int64_t tr = row < n ? row : n - 1;  // rows past n plan a copy and store nothing
+      const int L = plan_group(z, r, tr, plan, fb);
+      if (r == 0 && row < n) {
+        const bool au = audit_draw(row, plan);
+        plan.level[row] = (int8_t)L;
+        plan.audit[row] = au ? 1 : 0;
+        nv += 1;
+        nf += fb ? 1 : 0;
+        na += au ? 1 : 0;
+        lsum += (unsigned long long)L;
+      }
+    }
+  }
+  if (!kPlan) return;
+  for (int off = 32; off >= 16; off >>= 1) {  // the four group leaders (lanes 0, 16, 32, 48)
+    nv += __shfl_xor(nv, off, 64);
+    nf += __shfl_xor(nf, off, 64);
+    na += __shfl_xor(na, off, 64);
+    lsum += __shfl_xor(lsum, off, 64);
+  }
+  if (lane == 0 && nv) {
+    unsigned long long* sl = plan.slots + (blockIdx.x % kStatSlots) * kSlotU64;
+    atomicAdd(&sl[0], nv);
+    if (nf) atomicAdd(&sl[1], nf);
+    if (na) atomicAdd(&sl[2], na);
+    atomicAdd(&sl[3], lsum);
   }
 }
 
@@ -319,8 +432,16 @@ struct FeatVis {
 // their rounding.
 constexpr int kFeatStats = 15;  // col, len, slg, slg2, hist[10], segments
 __global__ __launch_bounds__(128) void k_features(TreeView T, CameraView C, int lc, int tiles_x, int tiles_y,
-                                                  float foot_log2, uint16_t* __restrict__ feat) {
+                                                  float foot_log2, uint16_t* __restrict__ feat,
+                                                  unsigned long long* __restrict__ zero_stats,
+                                                  unsigned long long* __restrict__ zero_slots) {
   __shared__ float part[kFeatStats * 64];
+  // the LOD render's statistics and counter slots start from zero here (the
+  // plan and the repair add to them later on the stream)
+  if (zero_stats && blockIdx.x == 0) {
+    if (threadIdx.x < 8) zero_stats[threadIdx.x] = 0;
+    for (int e = (int)threadIdx.x; e < kStatSlots * kSlotU64; e += (int)blockDim.x) zero_slots[e] = 0;
+  }
   const int lane = threadIdx.x & 63, w = (int)(threadIdx.x >> 6);
   const int tile = blockIdx.x * 4 + (lane >> 4), probe = lane & 15;
   const int ntiles = tiles_x * tiles_y;
@@ -431,60 +552,6 @@ __global__ __launch_bounds__(64) void k_labels(ImgPtrs I, int W, int H, int tile
   if (lane == 0) labels[tile] = (int8_t)label;
 }
 
-// ------------------------------------------------------------------ plan
-__device__ inline uint32_t hash32(uint64_t x) {
-  x += 0x9e3779b97f4a7c15ULL;
-  x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ULL;
-  x = (x ^ (x >> 27)) * 0x94d049bb133111ebULL;
-  return (uint32_t)((x ^ (x >> 31)) >> 32);
-}
-
-// stats: [0] tiles, [1] fallbacks, [2] audited, [3] violations, [4] level sum
-__global__ void k_plan(const float* __restrict__ logits, int ntiles, float q, float conf_thresh, int full_level,
-                       float audit_frac, uint64_t audit_seed, const int8_t* __restrict__ forced,
-                       int8_t* __restrict__ level, uint8_t* __restrict__ audit, unsigned long long* stats) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ntiles) return;
-  const float* z = logits + (int64_t)t * kOut;
-  float m = z[0];
-  for (int c = 1; c < kCls; ++c) m = fmaxf(m, z[c]);
-  float p[kCls], sum = 0.f;
-  for (int c = 0; c < kCls; ++c) {
-    p[c] = expf(z[c] - m);
-    sum += p[c];
-  }
-  float cdf = 0.f, pmax = 0.f;
-  int cls = kCls - 1;
-  bool found = false;
-  for (int c = 0; c < kCls; ++c) {
-    const float pc = p[c] / sum;
-    pmax = fmaxf(pmax, pc);
-    cdf += pc;
-    if (!found && cdf >= q) {
-      cls = c;
-      found = true;
-    }
-  }
-  int L = kLv0 + cls;
-  const bool fallback = !(pmax >= conf_thresh) || conf_thresh >= 1.f;
-  if (fallback) L = full_level;
-  if (forced) L = forced[t];
-  if (L > full_level) L = full_level;
-  if (L < 0) L = 0;
-  level[t] = (int8_t)L;
-  const bool a = audit_frac >= 1.f || (double)hash32(audit_seed * 0x100000001b3ULL + (uint64_t)t) <
-                                          (double)audit_frac * 4294967296.0;
-  audit[t] = a ? 1 : 0;
-  atomicAdd(&stats[0], 1ull);
-  if (fallback) atomicAdd(&stats[1], 1ull);
-  if (a) atomicAdd(&stats[2], 1ull);
-  atomicAdd(&stats[4], (unsigned long long)L);
-}
-
-__global__ void k_zero_stats(unsigned long long* s) {
-  if (threadIdx.x < 8) s[threadIdx.x] = 0;
-}
-
 // ----------------------------------------------------- render and audit
 // 8 x 8 packets (inside one 16 x 16 tile), tree truncated at the tile's
 // level, every ray walked in two spans by the block's two waves exactly as
@@ -555,23 +622,55 @@ template <int OP>
 __global__ __launch_bounds__(64) void k_audit_repair(RenderArgs A, const int8_t* __restrict__ level,
                                                      const uint8_t* __restrict__ audit, int tiles_x, float tol,
                                                      const float* __restrict__ full_out,
-                                                     const float* __restrict__ full_aux, unsigned long long* stats) {
+                                                     const float* __restrict__ full_aux, unsigned long long* stats,
+                                                     const unsigned long long* __restrict__ slots) {
   const int lane = threadIdx.x & 63;
-  const int packet = (int)blockIdx.x;
-  const int ty = packet / A.packets_x, tx = packet - ty * A.packets_x;
-  const int i = tx * 8 + (lane & 7), j = ty * 8 + (lane >> 3);
-  if (ty >= A.packets_y || i >= A.c.W || j >= A.c.H) return;
-  const int t = (ty * 8 / kTile) * tiles_x + (tx * 8 / kTile);
-  if (!(audit[t] && level[t] < A.max_level)) return;
-  const int64_t pix = (int64_t)j * A.c.W + i;
-  const float o = A.out[pix], of = full_out[pix];
-  const float d = fabsf(o - of);
-  const bool bad = of != 0.f ? d > tol * fabsf(of) : d != 0.f;
-  if (bad) {
-    A.out[pix] = of;
-    if (OP == kOpWMean && A.aux) A.aux[pix] = full_aux[pix];
-    atomicAdd(&stats[3], 1ull);
+  const int np = A.packets_x * A.packets_y;
+  if (blockIdx.x == 0) {  // the plan's counters: sum of the slots
+    static_assert(kStatSlots <= 64, "one lane per slot");
+    unsigned long long v[4] = {0, 0, 0, 0};
+    if (lane < kStatSlots)
+      for (int k = 0; k < 4; ++k) v[k] = slots[lane * kSlotU64 + k];
+    for (int off = 32; off > 0; off >>= 1)
+      for (int k = 0; k < 4; ++k) v[k] += __shfl_xor(v[k], off, 64);
+    if (lane == 0) {
+      stats[0] = v[0];
+      stats[1] = v[1];
+      stats[2] = v[2];
+      stats[4] = v[3];
+    }
   }
+  static_assert(kRepairPackets <= 64, "one lane per packet reads the flags");
+  // kRepairPackets consecutive packets per wave: lane k reads the flags of
+  // packet k's tile (one round trip), then the wave walks the flagged ones
+  const int pk = (int)blockIdx.x * kRepairPackets + lane;
+  bool flagged = false;
+  if (lane < kRepairPackets && pk < np) {
+    const int ty = pk / A.packets_x, tx = pk - ty * A.packets_x;
+    const int t = (ty * 8 / kTile) * tiles_x + (tx * 8 / kTile);
+    flagged = audit[t] && level[t] < A.max_level;
+  }
+  unsigned long long todo = __ballot(flagged);
+  unsigned long long nbad = 0;
+  while (todo) {
+    const int k = __ffsll((long long)todo) - 1;
+    todo &= todo - 1;
+    const int packet = (int)blockIdx.x * kRepairPackets + k;
+    const int ty = packet / A.packets_x, tx = packet - ty * A.packets_x;
+    const int i = tx * 8 + (lane & 7), j = ty * 8 + (lane >> 3);
+    if (i >= A.c.W || j >= A.c.H) continue;
+    const int64_t pix = (int64_t)j * A.c.W + i;
+    const float o = A.out[pix], of = full_out[pix];
+    const float d = fabsf(o - of);
+    const bool bad = of != 0.f ? d > tol * fabsf(of) : d != 0.f;
+    if (bad) {
+      A.out[pix] = of;
+      if (OP == kOpWMean && A.aux) A.aux[pix] = full_aux[pix];
+      ++nbad;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) nbad += __shfl_xor(nbad, off, 64);
+  if (lane == 0 && nbad) atomicAdd(&stats[3], nbad);
 }
 
 }  // namespace lod
@@ -761,8 +860,9 @@ int64_t amr_lod_tiles(int32_t W, int32_t H) {
   return (int64_t)((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile);
 }
 
-amr_status amr_lod_features(const amr_tree* t, const amr_camera* cam, int32_t coarse_level, uint16_t* feat,
-                            amr_stream s) {
+namespace {
+amr_status launch_features(const amr_tree* t, const amr_camera* cam, int32_t coarse_level, uint16_t* feat,
+                           unsigned long long* zero_stats, unsigned long long* zero_slots, amr_stream s) {
   if (!t || !cam || !feat) return fail(AMR_EINVAL, "null argument");
   if (t->info.host_only) return fail(AMR_EINVAL, "host_only tree");
   if (coarse_level < 0 || coarse_level > kMaxLevel || cam->W < 1 || cam->H < 1) return fail(AMR_EINVAL, "bad level");
@@ -779,17 +879,24 @@ amr_status amr_lod_features(const amr_tree* t, const amr_camera* cam, int32_t co
   const float fl2 = (float)std::log2(foot * std::ldexp(1.0, coarse_level) + 1e-30);
   const int ntiles = tx * ty;
   hipLaunchKernelGGL(k_features, dim3((ntiles + 3) / 4), dim3(128), 0, (hipStream_t)s, t->view, camera_view(*cam),
-                     coarse_level, tx, ty, fl2, feat);
+                     coarse_level, tx, ty, fl2, feat, zero_stats, zero_slots);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? AMR_OK : fail(AMR_EHIP, hipGetErrorString(e));
+}
+}  // namespace
+
+amr_status amr_lod_features(const amr_tree* t, const amr_camera* cam, int32_t coarse_level, uint16_t* feat,
+                            amr_stream s) {
+  return launch_features(t, cam, coarse_level, feat, nullptr, nullptr, s);
 }
 
 amr_status amr_lod_forward(const amr_lod_model* m, const uint16_t* feat, int64_t n, float* logits, uint16_t* acts,
                            amr_stream s) {
   if (!m || !feat || !logits || n < 0) return fail(AMR_EINVAL, "null argument");
   if (n == 0) return AMR_OK;
-  hipLaunchKernelGGL(k_fwd, dim3((unsigned)((n + 15) / 16)), dim3(64), 0, (hipStream_t)s, feat, n, m->Wb, m->P,
-                     logits, acts);
+  const unsigned blocks = (unsigned)((n + 16 * kFwdWaves - 1) / (16 * kFwdWaves));
+  hipLaunchKernelGGL(k_fwd<false>, dim3(blocks), dim3(64 * kFwdWaves), 0, (hipStream_t)s, feat, n, m->Wb, m->P,
+                     logits, acts, PlanArgs{});
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? AMR_OK : fail(AMR_EHIP, hipGetErrorString(e));
 }
@@ -866,10 +973,13 @@ amr_status amr_lod_labels(const float* const* imgs, int32_t W, int32_t H, float 
 // (fp32 [H][W] each: value, and weight for WMEAN).
 namespace {
 int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
-int64_t ws_planes_offset(int32_t W, int32_t H) {
+int64_t ws_slots_offset(int32_t W, int32_t H) {
   const int64_t nt = amr_lod_tiles(W, H);
   const int64_t n16 = (nt + 15) / 16 * 16;
   return align256(256 + n16 * kIn * 2 + n16 * kOut * 4 + 2 * n16 + 64);
+}
+int64_t ws_planes_offset(int32_t W, int32_t H) {
+  return ws_slots_offset(W, H) + (int64_t)kStatSlots * kSlotU64 * 8;
 }
 }  // namespace
 
@@ -902,13 +1012,15 @@ amr_status amr_render_lod(const amr_tree* t, const amr_camera* cam, amr_op op, c
   if (tile_levels) lev = tile_levels;
   unsigned long long* st = (unsigned long long*)stats;
   hipStream_t hs = (hipStream_t)s;
-  hipLaunchKernelGGL(k_zero_stats, dim3(1), dim3(64), 0, hs, st);
-  amr_status r = amr_lod_features(t, cam, std::min(c.coarse_level, cam->max_level), feat, s);
+  unsigned long long* slots = (unsigned long long*)(w + ws_slots_offset(cam->W, cam->H));
+  amr_status r = launch_features(t, cam, std::min(c.coarse_level, cam->max_level), feat, st, slots, s);
   if (r) return r;
-  r = amr_lod_forward(m, feat, nt, logits, nullptr, s);
-  if (r) return r;
-  hipLaunchKernelGGL(k_plan, dim3((nt + 255) / 256), dim3(256), 0, hs, logits, nt, c.quantile, c.conf_thresh,
-                     cam->max_level, c.audit_frac, (uint64_t)c.audit_seed, forced_levels, lev, aud, st);
+  // network and plan in one launch (k_fwd<true>): level and audit flag per tile
+  const PlanArgs pa{c.quantile, c.conf_thresh, cam->max_level, c.audit_frac, (uint64_t)c.audit_seed,
+                    forced_levels, lev, aud, slots};
+  const unsigned fb = (unsigned)((nt + 16 * kFwdWaves - 1) / (16 * kFwdWaves));
+  hipLaunchKernelGGL(k_fwd<true>, dim3(fb), dim3(64 * kFwdWaves), 0, hs, feat, (int64_t)nt, m->Wb, m->P, logits,
+                     nullptr, pa);
   RenderArgs a;
   a.t = t->view;
   a.c = camera_view(*cam);
@@ -923,19 +1035,20 @@ amr_status amr_render_lod(const amr_tree* t, const amr_camera* cam, amr_op op, c
   const unsigned np = (unsigned)(a.packets_x * a.packets_y);
   float* full_out = (float*)(w + ws_planes_offset(cam->W, cam->H));
   float* full_aux = (float*)((char*)full_out + align256((int64_t)cam->W * cam->H * 4));
+  const unsigned rb = (np + kRepairPackets - 1) / kRepairPackets;  // repair blocks
   if (op == AMR_SUM) {
     hipLaunchKernelGGL(k_render_tiles<kOpSum>, dim3(2 * np), dim3(128), 0, hs, a, lev, aud, tx, full_out, full_aux);
-    hipLaunchKernelGGL(k_audit_repair<kOpSum>, dim3(np), dim3(64), 0, hs, a, lev, aud, tx, c.rel_tol, full_out,
-                       full_aux, st);
+    hipLaunchKernelGGL(k_audit_repair<kOpSum>, dim3(rb), dim3(64), 0, hs, a, lev, aud, tx, c.rel_tol, full_out,
+                       full_aux, st, slots);
   } else if (op == AMR_MAX) {
     hipLaunchKernelGGL(k_render_tiles<kOpMax>, dim3(2 * np), dim3(128), 0, hs, a, lev, aud, tx, full_out, full_aux);
-    hipLaunchKernelGGL(k_audit_repair<kOpMax>, dim3(np), dim3(64), 0, hs, a, lev, aud, tx, c.rel_tol, full_out,
-                       full_aux, st);
+    hipLaunchKernelGGL(k_audit_repair<kOpMax>, dim3(rb), dim3(64), 0, hs, a, lev, aud, tx, c.rel_tol, full_out,
+                       full_aux, st, slots);
   } else {
     hipLaunchKernelGGL(k_render_tiles<kOpWMean>, dim3(2 * np), dim3(128), 0, hs, a, lev, aud, tx, full_out,
                        full_aux);
-    hipLaunchKernelGGL(k_audit_repair<kOpWMean>, dim3(np), dim3(64), 0, hs, a, lev, aud, tx, c.rel_tol, full_out,
-                       full_aux, st);
+    hipLaunchKernelGGL(k_audit_repair<kOpWMean>, dim3(rb), dim3(64), 0, hs, a, lev, aud, tx, c.rel_tol, full_out,
+                       full_aux, st, slots);
   }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? AMR_OK : fail(AMR_EHIP, hipGetErrorString(e));

@@ -63,7 +63,7 @@ def _lib():
 
 
 def default_config() -> dict:
-    return dict(coarse_level=7, quantile=0.99, conf_thresh=0.5, rel_tol=1e-3, audit_frac=0.02, audit_seed=0)
+    return dict(coarse_level=4, quantile=0.99, conf_thresh=0.5, rel_tol=1e-3, audit_frac=0.02, audit_seed=0)
 
 
 def tiles(W: int, H: int) -> int:
@@ -240,8 +240,10 @@ def train(model: LodModel, feat, lab, steps: int = 2000, batch: int = 8192, lr: 
 
 def evaluate(tree: Tree, desc: dict, model: Optional[LodModel], reps: int = 5, op: int = SUM) -> Dict:
     """Per-pixel error of the LOD render against full depth and the time of
-    both (HIP events; the LOD time includes features, network, plan, render
-    and audit)."""
+    both: after one warm-up call of each, the mean over `reps` calls issued
+    back to back (HIP events around the run, as in a render loop, so host
+    launch gaps are hidden alike); the LOD time includes features, network,
+    plan, render and audit."""
     import torch
 
     cam = set_camera(desc, tree)
@@ -253,21 +255,24 @@ def evaluate(tree: Tree, desc: dict, model: Optional[LodModel], reps: int = 5, o
     lev = torch.empty(tiles(cam.W, cam.H), dtype=torch.int8, device="cuda")
 
     def timed(fn):
-        ts = []
-        for r in range(reps + 1):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
             fn()
-            e1.record()
-            torch.cuda.synchronize()
-            if r:
-                ts.append(e0.elapsed_time(e1))
-        return float(np.median(ts))
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
 
-    t_plain = timed(lambda: render(tree, cam, op, full))
+    plain = lambda: render(tree, cam, op, full)
+    lod_fn = lambda: render_lod(tree, cam, op, model, out, ws, st, tile_levels=lev)
+    plain()
+    if model is not None:
+        lod_fn()
+    torch.cuda.synchronize()
+    t_plain = timed(plain)
     res = dict(t_plain_ms=t_plain)
     if model is not None:
-        t_lod = timed(lambda: render_lod(tree, cam, op, model, out, ws, st, tile_levels=lev))
+        t_lod = timed(lod_fn)
         f = full.double()
         d = (out.double() - f).abs()
         rel = torch.where(f != 0, d / f.abs().clamp_min(1e-300), torch.where(d == 0, 0.0, float("inf")))

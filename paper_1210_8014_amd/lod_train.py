@@ -32,7 +32,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def build_dataset(seeds, ncams, size, rng_seed=1234):
+def build_dataset(seeds, ncams, size, coarse_level, rng_seed=1234):
     import torch
 
     import amrgen
@@ -47,7 +47,7 @@ def build_dataset(seeds, ncams, size, rng_seed=1234):
         for _ in range(ncams):
             desc = amrgen.disk_camera(float(rng.uniform(0, 90)), size, size, max_level=16,
                                       azim_deg=float(rng.uniform(0, 360)))
-            f, l = lod.make_samples(T, desc)
+            f, l = lod.make_samples(T, desc, coarse_level=coarse_level)
             feats.append(f)
             labs.append(l)
         T.close()
@@ -98,6 +98,7 @@ def main():
     ap.add_argument("--quantile", type=float, default=0.99)
     ap.add_argument("--conf", type=float, default=0.5)
     ap.add_argument("--audit", type=float, default=0.02)
+    ap.add_argument("--coarse-level", type=int, default=None, help="probe level of the features (default: the config's)")
     ap.add_argument("--out", default=None)
     ap.add_argument("--model", default=None, help="evaluate this saved model instead of training one")
     ap.add_argument("--report", default=None)
@@ -109,14 +110,18 @@ def main():
 
     torch.cuda.set_device(0)
     cfg = dict(lod.default_config(), quantile=args.quantile, conf_thresh=args.conf, audit_frac=args.audit)
+    if args.coarse_level is not None:
+        cfg["coarse_level"] = args.coarse_level
     untrained = lod.LodModel(cfg, seed=11)
     if args.model:
         model = lod.LodModel(path=args.model)
+        if args.coarse_level is None:  # the probe level the model was trained with
+            cfg["coarse_level"] = model.config["coarse_level"]
         model.config = cfg
         hist, curve, t_train = np.zeros(16, np.int64), [], 0.0
     else:
         t0 = time.time()
-        feat, lab = build_dataset(_range(args.train_seeds), args.cams, args.size)
+        feat, lab = build_dataset(_range(args.train_seeds), args.cams, args.size, cfg["coarse_level"])
         hist = np.bincount(lab.cpu().numpy().astype(np.int64), minlength=16)
         log(f"dataset: {feat.shape[0]} tiles, label histogram (levels 1..16) {hist.tolist()} ({time.time() - t0:.0f} s)")
         model = lod.LodModel(cfg, seed=11)

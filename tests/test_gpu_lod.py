@@ -163,6 +163,58 @@ def _lod_setup(conf, audit, seed=0):
     return amr, lod, T, cam, m, full, ws, st
 
 
+def test_plan_matches_oracle():
+    """Per-tile levels of the LOD render (network and plan in one launch)
+    against the oracle's plan on the network's logits, for three quantile /
+    confidence settings.  The kernel takes the decisions in fp32 (shuffle
+    reductions), the oracle in fp64: tiles whose cumulative probability (or
+    top probability) lies within 1e-5 of the threshold may go either way and
+    must take one of the levels next to it; every other tile is equal."""
+    import oracle.lod as OL
+    import paper_1210_8014_amd as amr
+    from paper_1210_8014_amd import lod
+
+    leaves = amrgen.disk(seed=6, lmax=14, m_thr=3e-5)
+    T = amr.Tree(leaves)
+    cam = amr.set_camera(amrgen.disk_camera(60.0, 200, 136, max_level=14), T)
+    m = lod.LodModel(path=lod.MODEL_PATH)
+    nt = lod.tiles(cam.W, cam.H)
+    feat = torch.empty((nt, lod.NIN), dtype=torch.int16, device="cuda")
+    lod.features(T, cam, feat, min(m.config["coarse_level"], cam.max_level))
+    logits = torch.empty((nt, lod.NOUT), dtype=torch.float32, device="cuda")
+    m.forward(feat, nt, logits)
+    out = torch.empty(cam.W * cam.H, device="cuda")
+    ws = torch.empty(lod.workspace_bytes(cam.W, cam.H), dtype=torch.uint8, device="cuda")
+    st = torch.zeros(8, dtype=torch.int64, device="cuda")
+    lev = torch.empty(nt, dtype=torch.int8, device="cuda")
+    levels_seen = set()
+    for q, conf in ((0.99, 0.5), (0.7, 0.2), (0.3, 0.0)):
+        m.config = dict(quantile=q, conf_thresh=conf, audit_frac=0.0)
+        lod.render_lod(T, cam, amr.SUM, m, out, ws, st, tile_levels=lev)
+        torch.cuda.synchronize()
+        z = logits.cpu().numpy().astype(np.float64)
+        ref, fb = OL.plan(z, q, conf, cam.max_level)
+        p = OL.softmax10(z)
+        cdf = np.cumsum(p, axis=1)
+        near_q = np.abs(cdf - q) < 1e-5
+        near_c = np.abs(p.max(axis=1) - conf) < 1e-5
+        got = lev.cpu().numpy().astype(np.int64)
+        clear = ~near_q.any(axis=1) & ~near_c
+        assert clear.mean() > 0.95
+        assert np.array_equal(got[clear], ref[clear]), (q, conf)
+        for t in np.flatnonzero(~clear):  # either side of the boundary
+            alt = {int(ref[t]), cam.max_level} | {OL.LV0 + c for c in np.flatnonzero(near_q[t])}
+            alt |= {OL.LV0 + c + 1 for c in np.flatnonzero(near_q[t])}
+            assert int(got[t]) in alt, (q, conf, t)
+        s = st.cpu().numpy()
+        assert s[0] == nt and s[2] == 0 and s[4] == int(got.sum())
+        if not near_c.any():
+            assert s[1] == int(fb.sum())
+        levels_seen |= set(got.tolist())
+        log(f"q {q} conf {conf}: levels {np.bincount(got, minlength=15)}, fallbacks {s[1]}")
+    assert len(levels_seen) >= 4  # the settings exercise several classes
+
+
 def test_full_confidence_threshold_is_bit_identical_to_plain():
     amr, lod, T, cam, m, full, ws, st = _lod_setup(conf=1.0, audit=0.0)
     out = torch.empty_like(full)
@@ -197,15 +249,24 @@ def test_forced_wrong_levels_are_caught_by_the_audit():
     f, o = full.double(), out.double()
     rel = ((o - f).abs() / f.abs().clamp_min(1e-300))[f != 0]
     assert float(rel.max()) <= 1e-3
-    assert int(st[3].item()) > 0  # violations found and repaired
-    # without the audit the output is the plain render truncated at level 7
-    m.config = dict(audit_frac=0.0)
-    lod.render_lod(T, cam, amr.SUM, m, out, ws, st, forced=forced)
+    s = st.cpu().numpy()
+    assert s[0] == nt and s[1] == 0 and s[2] == nt and s[4] == 7 * nt
+    # the plain render truncated at level 7: the audit repairs exactly its
+    # pixels off by more than the tolerance (the audit's test, in fp32)
     c7 = amr.set_camera(dict(amrgen.disk_camera(60.0, 200, 136), max_level=7), T)
     r7 = torch.empty_like(full)
     amr.render(T, c7, amr.SUM, r7)
     torch.cuda.synchronize()
+    d = (r7 - full).abs()
+    bad = torch.where(full != 0, d > torch.tensor(1e-3, dtype=torch.float32) * full.abs(), d != 0)
+    assert int(bad.sum()) > 0 and s[3] == int(bad.sum())
+    assert torch.equal(out, torch.where(bad, full, r7))
+    # without the audit the output is the plain render truncated at level 7
+    m.config = dict(audit_frac=0.0)
+    lod.render_lod(T, cam, amr.SUM, m, out, ws, st, forced=forced)
+    torch.cuda.synchronize()
     assert torch.equal(out.view(torch.int32), r7.view(torch.int32))
+    assert st[2].item() == 0 and st[3].item() == 0
 
 
 def test_training_reduces_loss_and_model_roundtrips(tmp_path):
