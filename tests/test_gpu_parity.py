@@ -148,19 +148,28 @@ def test_gpu_deep_levels_fp64_boundaries():
     parity.compare_all(R, OT, cam, ops=("sum", "max"), trace_rays=np.arange(0, 65536, 11), what="deep")
 
 
-def test_gpu_disk_full_size_sampled():
-    """Galaxy disk, ~20.5M leaves, levels 7..16, 2048^2 perspective cameras at
-    inclinations 0/45/90: sum and line-of-sight mass-weighted velocity on a
-    seeded 1% ray sample; cell sequences of 2000 rays; determinism; every
-    kernel variant bit-identical."""
-    import paper_1210_8014_amd as amr
-
+@pytest.fixture(scope="module")
+def disk_full():
+    """The galaxy-disk scene at full size (library tree and oracle tree) and
+    the seeded 1% sample of the 2048^2 pixels, shared by the tests below."""
     log("generating disk")
     L = amrgen.scene("disk")
     R = _R(L)
     OT = oracle.Tree(L)
     n = 2048 * 2048
     rays = np.sort(np.random.default_rng(1).choice(n, n // 100, replace=False))
+    yield R, OT, rays
+    R.T.close()
+
+
+def test_gpu_disk_full_size_sampled(disk_full):
+    """Galaxy disk, ~20.5M leaves, levels 7..16, 2048^2 perspective cameras at
+    inclinations 0/45/90: sum and line-of-sight mass-weighted velocity on a
+    seeded 1% ray sample; cell sequences of 2000 rays; determinism; every
+    kernel variant bit-identical."""
+    import paper_1210_8014_amd as amr
+
+    R, OT, rays = disk_full
     for k, camd in enumerate(amrgen.disk_cameras()):
         log("disk camera", k)
         res = parity.compare_all(R, OT, camd, ops=("sum", "max", "wmean"), rays=rays, los_fields=(1, 0, True),
@@ -189,6 +198,52 @@ def test_gpu_disk_full_size_sampled():
     w1, x1 = R.full(cam, amr.WMEAN, field=1, weight=0, los=True)
     w2, x2 = R.full(cam, amr.WMEAN, field=1, weight=0, los=True)
     assert np.array_equal(w1.view(np.int32), w2.view(np.int32)) and np.array_equal(x1, x2)
+
+
+def test_gpu_disk_batch_launch_as_benched(disk_full):
+    """The benchmarked launch at full size: per op one batch over the three
+    2048^2 disk views (sum of density; line-of-sight velocity weighted by
+    density), in the grid shapes p8x8_fast_grid (the tuner's choice on this
+    workload) and p8x8_split2_grid: against the oracle on the seeded 1% ray
+    sample, and bit-identical to the per-image renders of the same walk."""
+    import paper_1210_8014_amd as amr
+
+    R, OT, rays = disk_full
+    descs = amrgen.disk_cameras()
+    cams = [R.camera(d) for d in descs]
+    n = 2048 * 2048
+    assert all(c.W * c.H == n for c in cams)
+    pairs = [(0, k) for k in range(len(cams))]
+    outs_s = [torch.full((n,), -7.0, device="cuda") for _ in cams]
+    outs_w = [torch.full((n,), -7.0, device="cuda") for _ in cams]
+    auxs = [torch.full((n,), -7.0, device="cuda") for _ in cams]
+    Bs = amr.Batch([R.T], cams, pairs, amr.SUM, outs_s, field=0)
+    Bw = amr.Batch([R.T], cams, pairs, amr.WMEAN, outs_w, auxs, field=1, weight=0, los=True)
+    refs = []
+    for k, camd in enumerate(descs):
+        ocam = OT.camera(camd)
+        refs.append((OT.render(ocam, oracle.SUM, rays=rays),
+                     OT.render(ocam, oracle.WMEAN, field=1, weight=0, los=True, rays=rays)))
+    names = amr.batch_configs()
+    for cfg, variant in (("p8x8_fast_grid", 0), ("p8x8_split2_grid", amr.variants().index("p8x8_split2_fast"))):
+        log("batch", cfg)
+        for x in outs_s + outs_w + auxs:
+            x.fill_(-7.0)
+        for B in (Bs, Bw):
+            B.set_config(names.index(cfg))
+            B.run()
+        torch.cuda.synchronize()
+        for k in range(len(cams)):
+            s_, w_, x_ = (t.cpu().numpy() for t in (outs_s[k], outs_w[k], auxs[k]))
+            parity.check_sum(s_[rays], refs[k][0]["val"], f"batch {cfg} cam{k} sum")
+            parity.check_wmean(w_[rays], x_[rays], refs[k][1], f"batch {cfg} cam{k} wmean")
+            a, _ = R.full(cams[k], amr.SUM, variant=variant)
+            w, x = R.full(cams[k], amr.WMEAN, field=1, weight=0, los=True, variant=variant)
+            assert np.array_equal(a.view(np.int32), s_.view(np.int32)), f"{cfg} cam{k} sum differs from the single render"
+            assert np.array_equal(w.view(np.int32), w_.view(np.int32)), f"{cfg} cam{k} wmean differs"
+            assert np.array_equal(x.view(np.int32), x_.view(np.int32)), f"{cfg} cam{k} weight differs"
+    Bs.close()
+    Bw.close()
 
 
 @pytest.mark.slow
