@@ -332,15 +332,18 @@ amr_status amr_lod_labels(const float* const* imgs, int32_t W, int32_t H, float 
 
 /* Render with the learned per-tile levels (tiles at or above the camera's
  * max_level render exactly like amr_render; audited tiles below it are also
- * rendered at full depth, in other blocks of the same launch, and a second
- * launch repairs their pixels).  Four launches: features, network and plan
- * (one kernel), tile render, repair.  workspace: device, 256-byte aligned, at
- * least amr_lod_workspace_bytes(W, H) (features, logits and plan of the
- * tiles, 4 KiB of counters, and two fp32 W x H planes for the audit).  tile_levels (device int8
- * [tiles] or NULL) receives the levels used; forced_levels (device int8
- * [tiles] or NULL) replaces the network's choice (tests of the audit).
+ * rendered at full depth when their render cut a cell, and a second launch
+ * repairs their pixels).  Four launches: features, network and plan
+ * (one kernel), tile render, repair.  workspace: device, 256-byte aligned,
+ * at least amr_lod_workspace_bytes(W, H) (features, logits and plan of the
+ * tiles, 4 KiB of counters, and two fp32 W x H planes for the audit).
+ * tile_levels (device int8 [tiles] or NULL) receives the levels used;
+ * forced_levels (device int8 [tiles] or NULL) replaces the network's choice
+ * (tests of the audit).
  * stats: device int64[8] overwritten with tiles, fallbacks, audited tiles,
- * overwritten pixels, sum of tile levels. */
+ * overwritten pixels, sum of tile levels, and audited 8 x 8 packets walked
+ * again at full depth (those with a ray that stopped its descent at a cell
+ * that has children; the others already are the full-depth image). */
 int64_t amr_lod_workspace_bytes(int32_t W, int32_t H);
 amr_status amr_render_lod(const amr_tree* t, const amr_camera* cam, amr_op op, const amr_lod_model* m,
                           const amr_render_opts* opts, float* out, float* aux, int8_t* tile_levels,

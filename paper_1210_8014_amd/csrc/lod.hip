@@ -556,68 +556,92 @@ __global__ __launch_bounds__(64) void k_labels(ImgPtrs I, int W, int H, int tile
 // 8 x 8 packets (inside one 16 x 16 tile), tree truncated at the tile's
 // level, every ray walked in two spans by the block's two waves exactly as
 // the default plain render does (a tile at full depth is bit-identical to
-// it).  The grid covers the packets twice.  The first half, dispatched
-// first, walks the packets of audited tiles (tiles below full depth picked
-// for checking) at full depth into the full-depth planes; the second half
-// walks every packet at its tile's level into out.  So the two walks of an
-// audited packet run in different blocks at the same time, and an audited
-// packet full of long rays does not double the image's tail.
+// it), packet rows dispatched from the middle of the image out.  The walk
+// records whether any ray cut a cell (stopped descending at a cell that has
+// children).  For a packet of an audited tile (a tile below full depth
+// picked for checking) that cut none, the image is the full-depth image
+// exactly (the same cells, chords and summation order) and is copied to the
+// full-depth planes; one that cut a cell is walked again at full depth by
+// the same block right away (stats[5] counts these), so that walk overlaps
+// the rest of the image instead of following it (k_render_tiles below).
+
+// One walk of a packet's rays with the tree truncated at lw: wave w walks
+// span w of its lane's ray (cut tracking on), wave 1 leaves its partial sums
+// in part for wave 0.
 template <int OP>
-__global__ __launch_bounds__(128) void k_render_tiles(RenderArgs A, const int8_t* __restrict__ level,
-                                                      const uint8_t* __restrict__ audit, int tiles_x,
-                                                      float* __restrict__ full_out, float* __restrict__ full_aux) {
-  __shared__ float part[4 * 64];
-  const int lane = threadIdx.x & 63, w = (int)(threadIdx.x >> 6);
-  // each half takes the packet rows from the middle of the image out, as the
-  // default plain render does
-  const int np = A.packets_x * A.packets_y;
-  const bool audit_half = (int)blockIdx.x < np;
-  const int packet = center_out(audit_half ? (int)blockIdx.x : (int)blockIdx.x - np, A.packets_x, A.packets_y);
-  const int ty = packet / A.packets_x, tx = packet - ty * A.packets_x;
-  const int i = tx * 8 + (lane & 7), j = ty * 8 + (lane >> 3);
-  const bool in = ty < A.packets_y && i < A.c.W && j < A.c.H;
-  // a packet lies inside one tile: its level and audit flag are block-uniform
-  const int t = (ty * 8 / kTile) * tiles_x + (tx * 8 / kTile);
-  const int L = level[t];
-  if (audit_half && !(audit[t] && L < A.max_level)) return;  // whole block
-  const int lw = audit_half ? A.max_level : L;
-  Partial P;
+__device__ __forceinline__ void tile_walk(const RenderArgs& A, int i, int j, bool in, int w, int lw, float* part,
+                                          Partial& P, bool& cut) {
   partial_init<OP>(P);
+  cut = false;
   Ray R;
   Entry E;
   if (in && setup_ray(A.c, i, j, R, E) && span_setup(R, E, A.t.base < lw ? A.t.base : lw, 2, w)) {
     if (w == 1)  // the last span runs to the box
-      walk_span<OP, true>(A.t, R, E, lw, A.field, A.wfield, A.los, P);
+      walk_span<OP, true, true>(A.t, R, E, lw, A.field, A.wfield, A.los, P, &cut);
     else
-      walk_span<OP>(A.t, R, E, lw, A.field, A.wfield, A.los, P);
+      walk_span<OP, false, true>(A.t, R, E, lw, A.field, A.wfield, A.los, P, &cut);
   }
   if (w == 1) {
-    float* q = part + lane;
+    float* q = part + (threadIdx.x & 63);
     q[0] = P.s0;
     q[64] = P.c0;
     q[128] = P.s1;
     q[192] = P.c1;
   }
-  __syncthreads();
-  if (w == 1 || !in) return;
-  const float* q = part + lane;
+}
+
+template <int OP>
+__device__ __forceinline__ void tile_finish(const float* part, Partial& P, float& o, float& x) {
+  const float* q = part + (threadIdx.x & 63);
   partial_merge<OP>(P, Partial{q[0], q[64], q[128], q[192]});
-  float o = 0.f, x = 0.f;
+  o = 0.f;
+  x = 0.f;
   partial_finish<OP>(P, o, x);
+}
+
+template <int OP>
+__global__ __launch_bounds__(128) void k_render_tiles(RenderArgs A, const int8_t* __restrict__ level,
+                                                      const uint8_t* __restrict__ audit, int tiles_x,
+                                                      float* __restrict__ full_out, float* __restrict__ full_aux,
+                                                      unsigned long long* __restrict__ stats) {
+  __shared__ float part[4 * 64];
+  const int lane = threadIdx.x & 63, w = (int)(threadIdx.x >> 6);
+  const int packet = center_out((int)blockIdx.x, A.packets_x, A.packets_y);
+  const int ty = packet / A.packets_x, tx = packet - ty * A.packets_x;
+  const int i = tx * 8 + (lane & 7), j = ty * 8 + (lane >> 3);
+  const bool in = ty < A.packets_y && i < A.c.W && j < A.c.H;
   const int64_t pix = (int64_t)j * A.c.W + i;
-  if (audit_half) {
-    full_out[pix] = o;
-    if (OP == kOpWMean) full_aux[pix] = x;
-  } else {
+  // a packet lies inside one tile: its level and audit flag are block-uniform
+  const int t = (ty * 8 / kTile) * tiles_x + (tx * 8 / kTile);
+  const int L = level[t];
+  const bool audited = audit[t] && L < A.max_level;
+  Partial P;
+  bool cut;
+  float o, x;
+  tile_walk<OP>(A, i, j, in, w, L, part, P, cut);
+  // (also the barrier for part) did a ray of either span cut a cell?
+  const bool again = audited ? __syncthreads_or(cut ? 1 : 0) != 0 : (__syncthreads(), false);
+  if (w == 0 && in) {
+    tile_finish<OP>(part, P, o, x);
     A.out[pix] = o;
     if (OP == kOpWMean && A.aux) A.aux[pix] = x;
+    if (audited && !again) {  // no cell cut: this is the full-depth image
+      full_out[pix] = o;
+      if (OP == kOpWMean) full_aux[pix] = x;
+    }
+  }
+  if (!again) return;  // block-uniform
+  if (threadIdx.x == 0) atomicAdd(&stats[5], 1ull);
+  __syncthreads();  // wave 0 has read part before wave 1 writes it again
+  tile_walk<OP>(A, i, j, in, w, A.max_level, part, P, cut);
+  __syncthreads();
+  if (w == 0 && in) {
+    tile_finish<OP>(part, P, o, x);
+    full_out[pix] = o;
+    if (OP == kOpWMean) full_aux[pix] = x;
   }
 }
 
-// Audit of the tiles rendered below full depth: a pixel of an audited tile
-// off by more than tol (relative to the full-depth value; any difference
-// when that is 0) takes the full-depth value and is counted.  One wave per
-// 8 x 8 packet; packets of other tiles return at once.
 template <int OP>
 __global__ __launch_bounds__(64) void k_audit_repair(RenderArgs A, const int8_t* __restrict__ level,
                                                      const uint8_t* __restrict__ audit, int tiles_x, float tol,
@@ -1037,16 +1061,18 @@ amr_status amr_render_lod(const amr_tree* t, const amr_camera* cam, amr_op op, c
   float* full_aux = (float*)((char*)full_out + align256((int64_t)cam->W * cam->H * 4));
   const unsigned rb = (np + kRepairPackets - 1) / kRepairPackets;  // repair blocks
   if (op == AMR_SUM) {
-    hipLaunchKernelGGL(k_render_tiles<kOpSum>, dim3(2 * np), dim3(128), 0, hs, a, lev, aud, tx, full_out, full_aux);
+    hipLaunchKernelGGL(k_render_tiles<kOpSum>, dim3(np), dim3(128), 0, hs, a, lev, aud, tx, full_out, full_aux,
+                       st);
     hipLaunchKernelGGL(k_audit_repair<kOpSum>, dim3(rb), dim3(64), 0, hs, a, lev, aud, tx, c.rel_tol, full_out,
                        full_aux, st, slots);
   } else if (op == AMR_MAX) {
-    hipLaunchKernelGGL(k_render_tiles<kOpMax>, dim3(2 * np), dim3(128), 0, hs, a, lev, aud, tx, full_out, full_aux);
+    hipLaunchKernelGGL(k_render_tiles<kOpMax>, dim3(np), dim3(128), 0, hs, a, lev, aud, tx, full_out, full_aux,
+                       st);
     hipLaunchKernelGGL(k_audit_repair<kOpMax>, dim3(rb), dim3(64), 0, hs, a, lev, aud, tx, c.rel_tol, full_out,
                        full_aux, st, slots);
   } else {
-    hipLaunchKernelGGL(k_render_tiles<kOpWMean>, dim3(2 * np), dim3(128), 0, hs, a, lev, aud, tx, full_out,
-                       full_aux);
+    hipLaunchKernelGGL(k_render_tiles<kOpWMean>, dim3(np), dim3(128), 0, hs, a, lev, aud, tx, full_out,
+                       full_aux, st);
     hipLaunchKernelGGL(k_audit_repair<kOpWMean>, dim3(rb), dim3(64), 0, hs, a, lev, aud, tx, c.rel_tol, full_out,
                        full_aux, st, slots);
   }

@@ -32,6 +32,7 @@
 // fp64.
 #pragma once
 #include <stdint.h>
+#include <type_traits>
 
 // Bounds assertions on every cell index, for CPU builds of this core only.
 #if defined(AMR_BOUNDS_CHECK)
@@ -476,6 +477,19 @@ AMR_HD uint32_t morton_inc(uint32_t m, int k, bool c) {
 // kWholeBox: the ray's stop planes are the box faces (R.stop = 2^28 on every
 // axis, as setup_ray leaves them), which makes the end test one comparison.
 // On return E is no longer the entry state of any cell.
+// Visitors that declare kTrackCut = true also learn whether the walk
+// stopped its descent at a cell that has children (a cell cut by the level
+// limit).  A walk that cut no cell visited exactly the cells, in the same
+// order and with the same chords, as a walk of the untruncated tree.
+template <class V, class = void>
+struct TracksCut {
+  static constexpr bool value = false;
+};
+template <class V>
+struct TracksCut<V, decltype((void)V::kTrackCut)> {
+  static constexpr bool value = V::kTrackCut;
+};
+
 template <class Vis, bool kWholeBox = false>
 AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_level, Vis& vis) {
   const int b0 = T.base < max_level ? T.base : max_level;
@@ -528,7 +542,10 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
       const ChildVal rec = T.cv[(uint32_t)node];
       v0 = rec.v0;
       const int32_t w = rec.child;
-      if (lvl >= max_level || w < 0) break;
+      if (lvl >= max_level || w < 0) {
+        if constexpr (TracksCut<Vis>::value) vis.cut_and &= w;  // sign bit clears at a cut
+        break;
+      }
       pfc = w;
       plv = lvl;
       ++lvl;
@@ -926,22 +943,45 @@ AMR_HD void partial_init(Partial& P) {
   P.c0 = P.s1 = P.c1 = 0.0f;
 }
 
+// Visitor V that also tracks cuts (TracksCut): cut_and is the bitwise AND of
+// the child index of every cell where the descent stopped, negative at a
+// leaf, so it stays negative exactly when no cell was cut.
+template <class V>
+struct CutVis : V {
+  static constexpr bool kTrackCut = true;
+  int32_t cut_and = -1;
+};
+template <bool kCut, class V>
+using CutIf = typename std::conditional<kCut, CutVis<V>, V>::type;
+template <class V>
+AMR_HD void take_cut(const V& v, bool* cut) {
+  if constexpr (TracksCut<V>::value) *cut = v.cut_and >= 0;
+}
+
 // kWholeBox: the span is the whole ray (no stop plane inside the box).
-template <int OP, bool kWholeBox = false>
+// kCut: *cut receives whether the walk cut a cell (TracksCut).
+template <int OP, bool kWholeBox = false, bool kCut = false>
 AMR_HD void walk_span(const TreeView& T, const Ray& R, Entry& E, int max_level, int field, int wfield, int los,
-                      Partial& P) {
+                      Partial& P, bool* cut = nullptr) {
   const int64_t nc = T.ncells;
   if (OP == kOpSum) {
-    SumVis v{T.val + (int64_t)field * nc, field == 0};
+    CutIf<kCut, SumVis> v;
+    v.v = T.val + (int64_t)field * nc;
+    v.field0 = field == 0;
     walk_fast<decltype(v), kWholeBox>(T, R, E, max_level, v);
     P.s0 = v.s;
     P.c0 = v.c;
+    take_cut(v, cut);
   } else if (OP == kOpMax) {
-    MaxVis v{T.val + (int64_t)field * nc, -INFINITY, field == 0};
+    CutIf<kCut, MaxVis> v;
+    v.v = T.val + (int64_t)field * nc;
+    v.m = -INFINITY;
+    v.field0 = field == 0;
     walk_fast<decltype(v), kWholeBox>(T, R, E, max_level, v);
     P.s0 = v.m;
+    take_cut(v, cut);
   } else {
-    WMeanVis v;
+    CutIf<kCut, WMeanVis> v;
     v.w = T.val + (int64_t)wfield * nc;
     v.f0 = T.val + (int64_t)field * nc;
     v.f1 = los ? v.f0 + nc : v.f0;
@@ -956,6 +996,7 @@ AMR_HD void walk_span(const TreeView& T, const Ray& R, Entry& E, int max_level, 
     P.c0 = v.cw;
     P.s1 = v.sf;
     P.c1 = v.cf;
+    take_cut(v, cut);
   }
 }
 

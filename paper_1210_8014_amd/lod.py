@@ -280,5 +280,5 @@ def evaluate(tree: Tree, desc: dict, model: Optional[LodModel], reps: int = 5, o
         res.update(t_lod_ms=t_lod, speedup=t_plain / t_lod, max_rel=float(rel.max()),
                    p999_rel=float(torch.quantile(rel[::7].float(), 0.999)), frac_bad=float((rel > 1e-3).double().mean()),
                    fallback_frac=float(s[1]) / max(1, s[0]), audited=int(s[2]), overwritten=int(s[3]),
-                   mean_level=float(s[4]) / max(1, s[0]))
+                   mean_level=float(s[4]) / max(1, s[0]), rewalked_packets=int(s[5]))
     return res

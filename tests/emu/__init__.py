@@ -79,6 +79,20 @@ class EmuTree:
                           ctypes.c_int64(len(rays)), _p(offs), _p(cells))
         return offs, cells[:int(offs[-1])]
 
+    def render_cut(self, cam, op, level, field=0, weight=0, los=False, rays=None):
+        """The learned-LOD tile walk at `level` (two spans per ray): values,
+        aux and whether each ray cut a cell."""
+        n = cam.W * cam.H if rays is None else len(rays)
+        pix = np.arange(n, dtype=np.int64) if rays is None else np.ascontiguousarray(rays, np.int64)
+        out = np.zeros(n, np.float32)
+        aux = np.zeros(n, np.float32)
+        cut = np.zeros(n, np.int32)
+        k4, ofuv = _cam_args(cam)
+        _load().emu_render_cut(*self._tree_args(), _p(k4), _p(ofuv), ctypes.c_int32(op), ctypes.c_int32(field),
+                               ctypes.c_int32(weight), ctypes.c_int32(int(los)), ctypes.c_int32(level), _p(pix),
+                               ctypes.c_int64(n), _p(out), _p(aux), _p(cut))
+        return out, aux, cut.astype(bool)
+
     def render_split(self, cam, op, K, field=0, weight=0, los=False, rays=None, with_cells=False):
         """Split-ray path (K spans per ray, merged in span order): values,
         aux, per-ray cell counts and, optionally, the concatenated cells."""

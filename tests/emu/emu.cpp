@@ -172,3 +172,56 @@ extern "C" int emu_render_split(const int32_t* child, const float* val, int64_t 
   });
   return 0;
 }
+
+// The learned-LOD tile walk: two spans per ray at level L, recording whether
+// any span cut a cell (a cell with children at which the descent stopped).
+template <int OP>
+static void cut_pixel(const TreeView& T, const CameraView& C, int field, int wfield, int los, int L, int i, int j,
+                      float& o, float& x, int32_t& cut) {
+  const int b0 = T.base < L ? T.base : L;
+  Partial P;
+  partial_init<OP>(P);
+  bool any = false;
+  for (int w = 0; w < 2; ++w) {
+    Partial Q;
+    partial_init<OP>(Q);
+    Ray R;
+    Entry E;
+    bool c = false;
+    if (setup_ray(C, i, j, R, E) && span_setup(R, E, b0, 2, w)) {
+      if (w == 1)
+        walk_span<OP, true, true>(T, R, E, L, field, wfield, los, Q, &c);
+      else
+        walk_span<OP, false, true>(T, R, E, L, field, wfield, los, Q, &c);
+    }
+    any = any || c;
+    if (w == 0)
+      P = Q;
+    else
+      partial_merge<OP>(P, Q);
+  }
+  o = 0.0f;
+  x = 0.0f;
+  partial_finish<OP>(P, o, x);
+  cut = any ? 1 : 0;
+}
+
+extern "C" int emu_render_cut(const int32_t* child, const float* val, int64_t ncells, int32_t nfields, int32_t base,
+                              int32_t lmax, const int32_t* off, const int32_t* cam4, const int64_t* ofuv, int32_t op,
+                              int32_t field, int32_t wfield, int32_t los, int32_t level, const int64_t* pix, int64_t n,
+                              float* out, float* aux, int32_t* cut) {
+  const TreeView T = make_tree(child, val, ncells, nfields, base, lmax, off);
+  const CameraView C = make_cam(cam4, ofuv);
+  par(n, [&](int64_t r) {
+    const int i = (int)(pix[r] % C.W), j = (int)(pix[r] / C.W);
+    float o, x;
+    int32_t c;
+    if (op == 0) cut_pixel<kOpSum>(T, C, field, wfield, los, level, i, j, o, x, c);
+    else if (op == 1) cut_pixel<kOpMax>(T, C, field, wfield, los, level, i, j, o, x, c);
+    else cut_pixel<kOpWMean>(T, C, field, wfield, los, level, i, j, o, x, c);
+    out[r] = o;
+    aux[r] = x;
+    cut[r] = c;
+  });
+  return 0;
+}

@@ -193,3 +193,48 @@ def test_whole_box_end_test_matches_per_axis_end_test():
         b, _, cb, _ = E.render_split(cam, 0, 1, rays=rays)
         assert ca.sum() > 10 * len(rays)
         assert np.array_equal(a.view(np.int32), b.view(np.int32)) and np.array_equal(ca, cb)
+
+
+def _cells_per_ray(offs, cells):
+    return [cells[offs[r]:offs[r + 1]].tobytes() for r in range(len(offs) - 1)]
+
+
+def test_lod_cut_flag_is_exactly_the_rays_that_differ_from_full_depth():
+    """The learned-LOD tile walk records whether a ray cut a cell (stopped
+    descending at a cell that has children).  A ray that cut none must give
+    the full-depth result bit for bit (the LOD render then copies it instead
+    of walking the ray again for its audit); a ray that cut one must have a
+    cell sequence different from the full-depth one."""
+    rng = np.random.default_rng(91)
+    seen = [0, 0]
+    cases = []
+    for seed in (31, 32, 33):
+        L = amrgen.random_tree(seed, lmax=6, p_refine=0.45, nfields=4)
+        L.fields[1:] -= 5.0
+        cases.append((L, rand_cams(rng, 3, W=21, H=17, inside=(seed % 2 == 0)) + degenerate_cams()))
+    cases.append((amrgen.disk(seed=3, lmax=11, m_thr=2e-4), amrgen.disk_cameras(40, 40, max_level=11)))
+    for L, cams in cases:
+        T = amr.Tree(L, host_only=True)
+        E = emu.EmuTree(T)
+        lmax = int(T.info.lmax)
+        for camd in cams:
+            cam = amr.set_camera(dict(camd, max_level=lmax), T)
+            rays = np.arange(cam.W * cam.H)
+            ref_cells = _cells_per_ray(*E.trace(cam, rays))
+            for op, kw in ((0, {}), (1, {}), (2, dict(field=1, weight=0, los=True))):
+                if op == 2 and T.info.nfields < 4:
+                    continue
+                full, full_aux, _, _ = E.render_split(cam, op, 2, **kw)
+                for lv in range(0, lmax):
+                    out, aux, cut = E.render_cut(cam, op, lv, **kw)
+                    keep = ~cut
+                    assert np.array_equal(out[keep].view(np.int32), full[keep].view(np.int32)), (lv, op)
+                    assert np.array_equal(aux[keep].view(np.int32), full_aux[keep].view(np.int32)), (lv, op)
+                    if op == 0:
+                        cl = amr.set_camera(dict(camd, max_level=lv), T)
+                        cells = _cells_per_ray(*E.trace(cl, rays))
+                        differs = np.array([a != b for a, b in zip(cells, ref_cells)])
+                        assert np.array_equal(cut, differs), (lv, np.flatnonzero(cut != differs)[:5])
+                        seen[0] += int(cut.sum())
+                        seen[1] += int(keep.sum())
+    assert seen[0] > 1000 and seen[1] > 1000  # both kinds of ray occur

@@ -261,6 +261,16 @@ def test_forced_wrong_levels_are_caught_by_the_audit():
     bad = torch.where(full != 0, d > torch.tensor(1e-3, dtype=torch.float32) * full.abs(), d != 0)
     assert int(bad.sum()) > 0 and s[3] == int(bad.sum())
     assert torch.equal(out, torch.where(bad, full, r7))
+    # only the packets with a ray that cut a cell are walked again at full
+    # depth (the others are the full-depth image already): count them with
+    # the CPU build of the same walk
+    from tests import emu
+
+    Th = amr.Tree(amrgen.disk(seed=6, lmax=14, m_thr=3e-5), host_only=True)
+    _, _, cut = emu.EmuTree(Th).render_cut(amr.set_camera(amrgen.disk_camera(60.0, 200, 136, max_level=14), Th), 0, 7)
+    cut = cut.reshape(cam.H, cam.W)
+    packets = [cut[y:y + 8, x:x + 8].any() for y in range(0, cam.H, 8) for x in range(0, cam.W, 8)]
+    assert sum(packets) > 0 and s[5] == sum(packets)
     # without the audit the output is the plain render truncated at level 7
     m.config = dict(audit_frac=0.0)
     lod.render_lod(T, cam, amr.SUM, m, out, ws, st, forced=forced)
