@@ -11,10 +11,11 @@
 //   network   32 -> 64 -> 64 -> 64 -> 16 (16 classes = levels 1..16), ReLU,
 //             bf16 weights and activations, fp32 accumulation on
 //             v_mfma_f32_16x16x32_bf16;
-//   plan      softmax; level = first class whose cumulative probability
-//             reaches q; tiles whose top probability is below a confidence
-//             threshold fall back to full depth; a seeded fraction of tiles
-//             is audited (rendered again at full depth and compared, pixels
+//   plan      (in the network's kernel) softmax; level = first class whose
+//             cumulative probability reaches q; tiles whose top probability
+//             is below a confidence threshold fall back to full depth; a
+//             seeded fraction of tiles is audited (where the tile render
+//             cut a cell, rendered again at full depth and compared, pixels
 //             off by more than the tolerance overwritten and counted);
 //   training  labels from plain renders at every level, cross-entropy with
 //             an extra penalty on the probability of too-shallow levels,
