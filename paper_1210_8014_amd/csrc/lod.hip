@@ -71,28 +71,13 @@ __device__ inline f32x4 mfma(const u16x8& a, const u16x8& b, f32x4 c) {
                                                  0, 0);
 }
 
-// One 16 x 16 output block of a 16-row activation tile (A, row-major in LDS,
-// row stride lda, K = nk * 32) times B = W[k][col0 + n] (row-major, ldb),
-// K rows in [0, kvalid).  MFMA operand layout: lane l owns A row l % 16 and B
-// column l % 16, eight consecutive k starting at 8 (l / 16); it receives D
-// rows 4 (l / 16) .. +3 of column l % 16.
-__device__ inline f32x4 block_lds_x_w(const uint16_t* A, int lda, const uint16_t* W, int ldb, int col0, int nk,
-                                      int kvalid) {
-  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  for (int ks = 0; ks < nk; ++ks) {
-    u16x8 a, b;
-    for (int j = 0; j < 8; ++j) {
-      const int k = ks * 32 + g * 8 + j;
-      a[j] = k < kvalid ? A[r * lda + k] : (uint16_t)0;
-      b[j] = k < kvalid ? W[k * ldb + col0 + r] : (uint16_t)0;
-    }
-    acc = mfma(a, b, acc);
-  }
-  return acc;
-}
+// MFMA operand layout (v_mfma_f32_16x16x32_bf16): lane l owns A row l % 16
+// and B column l % 16, eight consecutive k starting at 8 (l / 16); it
+// receives D rows 4 (l / 16) .. +3 of column l % 16.
 
-// Same with B = W^T: B[k][n] = W[(col0 + n) * ldw + k].
+// One 16 x 16 output block of a 16-row activation tile (A, row-major in LDS,
+// row stride lda, K = nk * 32, rows k < kvalid) times B = W^T:
+// B[k][n] = W[(col0 + n) * ldw + k].
 __device__ inline f32x4 block_lds_x_wt(const uint16_t* A, int lda, const uint16_t* W, int ldw, int col0, int nk,
                                        int kvalid) {
   const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
@@ -168,96 +153,115 @@ __device__ inline bool audit_draw(int64_t t, const PlanArgs& A) {
 }
 
 // --------------------------------------------------------------- forward
-// One block = kFwdWaves waves, each computing 16 samples through the four
-// layers; the weights and biases are staged in LDS once per block, so every
-// layer reads its operands from LDS (no chain of dependent global loads).
-// X: [n][32] bf16.  Wb: bf16 weights, P: fp32 parameters (biases).
-// logits: [n][16] fp32.  acts (optional): [3][n][64] bf16 post-ReLU
-// activations, for the backward pass.  kPlan: the wave then plans its 16
-// tiles from the logits in its registers (plan_group, one 16-lane group per
-// tile) and adds its counts to one of the statistics slots.
+// A 16-row activation tile (A, row-major in LDS, row stride kHid, K = nk *
+// 32) times this lane's B operand held in registers (b[ks]: the eight
+// weights of column l % 16, rows ks * 32 + 8 (l / 16) .. +7).
+__device__ inline f32x4 lds_rows_x_regs(const uint16_t* A, const u16x8* b, int nk) {
+  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (int ks = 0; ks < nk; ++ks) {
+    u16x8 a;
+    for (int j = 0; j < 8; ++j) a[j] = A[r * kHid + ks * 32 + g * 8 + j];
+    acc = mfma(a, b[ks], acc);
+  }
+  return acc;
+}
+
+// One block = 16 samples, kFwdWaves = 4 waves.  Wave v computes columns
+// 16 v .. 16 v + 15 of each hidden layer, with its weight columns and biases
+// loaded into registers once at the start; the block exchanges the layers'
+// activations through LDS.  Every wave computes the 16 logits (one column
+// block) of the 16 samples.  X: [n][32] bf16.  Wb: bf16 weights, P: fp32
+// parameters (biases).  logits: [n][16] fp32 (written by wave 0).  acts
+// (optional): [3][n][64] bf16 post-ReLU activations, for the backward pass.
+// kPlan: wave v then plans samples 4 g + v (plan_group, lane group g) and the
+// block adds its counts to one of the statistics slots.
 constexpr int kFwdWaves = 4;
+static_assert(kFwdWaves * 16 == kHid, "one column block of the hidden layers per wave");
 template <bool kPlan>
 __global__ __launch_bounds__(64 * kFwdWaves) void k_fwd(const uint16_t* __restrict__ X, int64_t n,
                                                         const uint16_t* __restrict__ Wb,
                                                         const float* __restrict__ P, float* __restrict__ logits,
                                                         uint16_t* __restrict__ acts, PlanArgs plan) {
-  static_assert(kParams % 8 == 0, "weights are staged in 16-byte pieces");
-  __shared__ uint4 sW4[kParams / 8];              // bf16 weights (the bias slots are not read)
-  __shared__ float sBias[3 * kHid + kOut];        // b1 | b2 | b3 | b4
-  __shared__ uint16_t act[kFwdWaves][2][16 * kHid];
-  const int lane = threadIdx.x & 63, wv = (int)(threadIdx.x >> 6), r = lane & 15, g = lane >> 4;
-  for (int e = (int)threadIdx.x; e < kParams / 8; e += 64 * kFwdWaves) sW4[e] = ((const uint4*)Wb)[e];
-  for (int e = (int)threadIdx.x; e < 3 * kHid + kOut; e += 64 * kFwdWaves)
-    sBias[e] = P[e < kHid ? oB1 + e : e < 2 * kHid ? oB2 + (e - kHid) : e < 3 * kHid ? oB3 + (e - 2 * kHid)
-                                                                                    : oB4 + (e - 3 * kHid)];
-  const uint16_t* sW = (const uint16_t*)sW4;
-  const int64_t r0 = ((int64_t)blockIdx.x * kFwdWaves + wv) * 16;
-  uint16_t* in = act[wv][0];
-  uint16_t* out = act[wv][1];
-  // stage the wave's input rows
-  for (int e = lane; e < 16 * kIn; e += 64) {
+  static_assert(kIn == 32 && kHid == 64 && kOut == 16, "operand layout of this kernel");
+  __shared__ uint16_t act[2][16 * kHid];
+  __shared__ unsigned long long cnt[kFwdWaves][4];
+  const int lane = threadIdx.x & 63, v = (int)(threadIdx.x >> 6), r = lane & 15, g = lane >> 4;
+  const int64_t r0 = (int64_t)blockIdx.x * 16;
+  const int col = v * 16 + r;
+  // this lane's B operands: rows ks * 32 + 8 g + j of its column
+  u16x8 b1[1], b2[2], b3[2], b4[2];
+  for (int j = 0; j < 8; ++j) {
+    b1[0][j] = Wb[oW1 + (g * 8 + j) * kHid + col];
+    for (int ks = 0; ks < 2; ++ks) {
+      const int k = ks * 32 + g * 8 + j;
+      b2[ks][j] = Wb[oW2 + k * kHid + col];
+      b3[ks][j] = Wb[oW3 + k * kHid + col];
+      b4[ks][j] = Wb[oW4 + k * kOut + r];
+    }
+  }
+  const float bias[3] = {P[oB1 + col], P[oB2 + col], P[oB3 + col]};
+  const float bias4 = P[oB4 + r];
+  // the input rows (row stride kHid)
+  for (int e = (int)threadIdx.x; e < 16 * kIn; e += 64 * kFwdWaves) {
     const int row = e / kIn, k = e % kIn;
-    in[row * kHid + k] = r0 + row < n ? X[(r0 + row) * kIn + k] : (uint16_t)0;
+    act[0][row * kHid + k] = r0 + row < n ? X[(r0 + row) * kIn + k] : (uint16_t)0;
   }
   __syncthreads();
-#pragma unroll 1
   for (int L = 0; L < 3; ++L) {
-    const int wofs = L == 0 ? oW1 : L == 1 ? oW2 : oW3, kin = L == 0 ? kIn : kHid;
-#pragma unroll 1
-    for (int cb = 0; cb < kHid / 16; ++cb) {
-      f32x4 acc = block_lds_x_w(in, kHid, sW + wofs, kHid, cb * 16, kin / 32, kin);
-      const int col = cb * 16 + r;
-      const float bias = sBias[L * kHid + col];
-      for (int i = 0; i < 4; ++i) {
-        const int row = g * 4 + i;
-        float v = acc[i] + bias;
-        v = v > 0.f ? v : 0.f;
-        const uint16_t h = f2bf(v);
-        out[row * kHid + col] = h;
-        if (acts && r0 + row < n) acts[((int64_t)L * n + r0 + row) * kHid + col] = h;
-      }
+    const uint16_t* in = act[L & 1];
+    uint16_t* out = act[(L + 1) & 1];
+    const f32x4 acc = L == 0 ? lds_rows_x_regs(in, b1, 1) : lds_rows_x_regs(in, L == 1 ? b2 : b3, 2);
+    for (int i = 0; i < 4; ++i) {
+      const int row = g * 4 + i;
+      float x = acc[i] + bias[L];
+      x = x > 0.f ? x : 0.f;
+      const uint16_t h = f2bf(x);
+      out[row * kHid + col] = h;
+      if (acts && r0 + row < n) acts[((int64_t)L * n + r0 + row) * kHid + col] = h;
     }
     __syncthreads();
-    uint16_t* t = in;
-    in = out;
-    out = t;
   }
-  f32x4 acc = block_lds_x_w(in, kHid, sW + oW4, kOut, 0, kHid / 32, kHid);
-  unsigned long long nv = 0, nf = 0, na = 0, lsum = 0;  // counted by lane r = 0 of each group
-  for (int i = 0; i < 4; ++i) {
-    const int64_t row = r0 + g * 4 + i;
-    const float z = acc[i] + sBias[3 * kHid + r];
-    if (row < n) logits[row * kOut + r] = z;
-    if (kPlan) {
-      // lane group g holds the 16 class logits of row g * 4 + i, lane r class r
-      bool fb;
-      const int64_t tr = row < n ? row : n - 1;  // rows past n plan a copy and store nothing
-      const int L = plan_group(z, r, tr, plan, fb);
-      if (r == 0 && row < n) {
-        const bool au = audit_draw(row, plan);
-        plan.level[row] = (int8_t)L;
-        plan.audit[row] = au ? 1 : 0;
-        nv += 1;
-        nf += fb ? 1 : 0;
-        na += au ? 1 : 0;
-        lsum += (unsigned long long)L;
-      }
+  const f32x4 acc = lds_rows_x_regs(act[1], b4, 2);
+  if (v == 0)
+    for (int i = 0; i < 4; ++i) {
+      const int64_t row = r0 + g * 4 + i;
+      if (row < n) logits[row * kOut + r] = acc[i] + bias4;
     }
-  }
   if (!kPlan) return;
+  // wave v plans sample 4 g + v: lane group g holds its 16 class logits
+  const float z = (v == 0 ? acc[0] : v == 1 ? acc[1] : v == 2 ? acc[2] : acc[3]) + bias4;
+  const int64_t row = r0 + g * 4 + v;
+  const int64_t tr = row < n ? row : n - 1;  // rows past n plan a copy and store nothing
+  bool fb;
+  const int L = plan_group(z, r, tr, plan, fb);
+  unsigned long long nv = 0, nf = 0, na = 0, lsum = 0;  // counted by lane r = 0 of each group
+  if (r == 0 && row < n) {
+    const bool au = audit_draw(row, plan);
+    plan.level[row] = (int8_t)L;
+    plan.audit[row] = au ? 1 : 0;
+    nv = 1;
+    nf = fb ? 1 : 0;
+    na = au ? 1 : 0;
+    lsum = (unsigned long long)L;
+  }
   for (int off = 32; off >= 16; off >>= 1) {  // the four group leaders (lanes 0, 16, 32, 48)
     nv += __shfl_xor(nv, off, 64);
     nf += __shfl_xor(nf, off, 64);
     na += __shfl_xor(na, off, 64);
     lsum += __shfl_xor(lsum, off, 64);
   }
-  if (lane == 0 && nv) {
-    unsigned long long* sl = plan.slots + (blockIdx.x % kStatSlots) * kSlotU64;
-    atomicAdd(&sl[0], nv);
-    if (nf) atomicAdd(&sl[1], nf);
-    if (na) atomicAdd(&sl[2], na);
-    atomicAdd(&sl[3], lsum);
+  if (lane == 0) {
+    cnt[v][0] = nv;
+    cnt[v][1] = nf;
+    cnt[v][2] = na;
+    cnt[v][3] = lsum;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {  // the block's counts, one atomic each
+    unsigned long long t = 0;
+    for (int w = 0; w < kFwdWaves; ++w) t += cnt[w][threadIdx.x];
+    if (t) atomicAdd(&plan.slots[(blockIdx.x % kStatSlots) * kSlotU64 + threadIdx.x], t);
   }
 }
 
@@ -919,7 +923,7 @@ amr_status amr_lod_forward(const amr_lod_model* m, const uint16_t* feat, int64_t
                            amr_stream s) {
   if (!m || !feat || !logits || n < 0) return fail(AMR_EINVAL, "null argument");
   if (n == 0) return AMR_OK;
-  const unsigned blocks = (unsigned)((n + 16 * kFwdWaves - 1) / (16 * kFwdWaves));
+  const unsigned blocks = (unsigned)((n + 15) / 16);
   hipLaunchKernelGGL(k_fwd<false>, dim3(blocks), dim3(64 * kFwdWaves), 0, (hipStream_t)s, feat, n, m->Wb, m->P,
                      logits, acts, PlanArgs{});
   hipError_t e = hipGetLastError();
@@ -1043,7 +1047,7 @@ amr_status amr_render_lod(const amr_tree* t, const amr_camera* cam, amr_op op, c
   // network and plan in one launch (k_fwd<true>): level and audit flag per tile
   const PlanArgs pa{c.quantile, c.conf_thresh, cam->max_level, c.audit_frac, (uint64_t)c.audit_seed,
                     forced_levels, lev, aud, slots};
-  const unsigned fb = (unsigned)((nt + 16 * kFwdWaves - 1) / (16 * kFwdWaves));
+  const unsigned fb = (unsigned)((nt + 15) / 16);
   hipLaunchKernelGGL(k_fwd<true>, dim3(fb), dim3(64 * kFwdWaves), 0, hs, feat, (int64_t)nt, m->Wb, m->P, logits,
                      nullptr, pa);
   RenderArgs a;
