@@ -605,7 +605,7 @@ __device__ __forceinline__ void tile_finish(const float* part, Partial& P, float
 }
 
 template <int OP>
-__global__ __launch_bounds__(128) void k_render_tiles(RenderArgs A, const int8_t* __restrict__ level,
+__global__ __launch_bounds__(128, OP == kOpWMean ? 7 : 8) void k_render_tiles(RenderArgs A, const int8_t* __restrict__ level,
                                                       const uint8_t* __restrict__ audit, int tiles_x,
                                                       float* __restrict__ full_out, float* __restrict__ full_aux,
                                                       unsigned long long* __restrict__ stats) {

@@ -123,6 +123,19 @@ AMR_HD uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
 }
 
 AMR_HD int64_t mul64(int32_t a, int32_t b) { return (int64_t)a * (int64_t)b; }
+
+// floor(num / d) for 0 <= num < 2^28 d and 0 < d < 2^31 (quotient below
+// 2^28), exactly: the fp64 quotient of the converted operands is within
+// 2^-24 of the true one (num's conversion and the division each add a
+// relative error of at most 2^-53 to a value below 2^28), so its truncation
+// is the quotient or one off, and one integer remainder test corrects it.
+// A few dozen instructions instead of a generic 64-bit division.
+AMR_HD int32_t div_q28(int64_t num, int32_t d) {
+  int32_t q = (int32_t)((double)num / (double)d);
+  const int64_t rem = num - mul64(q, d);
+  q += rem < 0 ? -1 : (rem >= d ? 1 : 0);
+  return q;
+}
 #if !defined(__HIPCC__)
 inline int min(int a, int b) { return a < b ? a : b; }
 #endif
@@ -258,7 +271,7 @@ AMR_HD bool setup_ray(const CameraView& C, int i, int j, Ray& R, Entry& E) {
     } else {
       // floor(x_k) at the entry: (o_k d_a - o_a d_k) / d_a, numerator in [0, 2^28 d_a)
       const int64_t num = mul64(R.o[k], ed) - mul64(oa, R.d[k]);
-      E.p[k] = (int32_t)((uint64_t)num / (uint64_t)(uint32_t)ed);
+      E.p[k] = div_q28(num, ed);
     }
   }
   E.a = a;
@@ -863,8 +876,9 @@ AMR_HD bool plane_entry(const Ray& R, int a, int32_t P, Entry& E) {
   for (int k = 0; k < 3; ++k) {
     // x_k at the crossing = (o_k d_a + (P - o_a) d_k) / d_a, in [0, 2^28)
     const int64_t num = (int64_t)R.o[k] * da + dt * (int64_t)R.d[k];
-    if (k != a && num >= (int64_t)kOne * da) inside = false;
-    p[k] = k == a ? P : (int32_t)((uint64_t)(num < 0 ? 0 : num) / (uint64_t)da);
+    const bool beyond = num >= (int64_t)kOne * da;  // outside the box (then p is not used)
+    if (k != a && beyond) inside = false;
+    p[k] = k == a ? P : div_q28(num < 0 || beyond ? 0 : num, da32);
   }
   if (!inside) return false;
   E.p[0] = p[0];

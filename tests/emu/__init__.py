@@ -38,6 +38,15 @@ def _cam_args(cam):
     return k4, ofuv
 
 
+def div_q28(num, d):
+    """floor(num / d) by the traversal core's helper (0 <= num < 2^28 d)."""
+    num = np.ascontiguousarray(num, np.int64)
+    d = np.ascontiguousarray(d, np.int32)
+    q = np.zeros(len(num), np.int32)
+    _load().emu_div_q28(_p(num), _p(d), _p(q), ctypes.c_int64(len(num)))
+    return q
+
+
 class EmuTree:
     """Host arrays of a host_only library tree plus its layout constants."""
 

@@ -225,3 +225,8 @@ extern "C" int emu_render_cut(const int32_t* child, const float* val, int64_t nc
   });
   return 0;
 }
+
+// The exact quotient helper of the ray set-up, for its own test.
+extern "C" void emu_div_q28(const int64_t* num, const int32_t* d, int32_t* q, int64_t n) {
+  for (int64_t r = 0; r < n; ++r) q[r] = div_q28(num[r], d[r]);
+}

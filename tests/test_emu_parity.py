@@ -238,3 +238,24 @@ def test_lod_cut_flag_is_exactly_the_rays_that_differ_from_full_depth():
                         seen[0] += int(cut.sum())
                         seen[1] += int(keep.sum())
     assert seen[0] > 1000 and seen[1] > 1000  # both kinds of ray occur
+
+
+def test_exact_quotient_of_the_ray_setup():
+    """The set-up's floor(num / d) (an fp64 estimate corrected once) against
+    integer division, over its whole domain 0 <= num < 2^28 d, 0 < d < 2^31:
+    random operands, exact multiples and their neighbours, the extremes."""
+    rng = np.random.default_rng(17)
+    d = np.concatenate([rng.integers(1, 2 ** 31, 200_000), rng.integers(1, 64, 20_000),
+                        [1, 2, 3, 2 ** 31 - 1, 2 ** 30, 2 ** 31 - 2]]).astype(np.int64)
+    q = rng.integers(0, 2 ** 28, len(d))
+    q[-6:] = [0, 2 ** 28 - 1, 1, 2 ** 28 - 1, 2 ** 27, 12345]
+    cases = []
+    for off in (-1, 0, 1):  # just below, at and just above an exact multiple
+        cases.append((q * d + off, d))
+    cases.append((q * d + (rng.random(len(d)) * d).astype(np.int64), d))
+    cases.append((d * (2 ** 28) - 1, d))  # the largest numerator
+    for num, dd in cases:
+        ok = (num >= 0) & (num < dd * 2 ** 28)
+        num, dd = num[ok], dd[ok]
+        got = emu.div_q28(num, dd.astype(np.int32))
+        assert np.array_equal(got.astype(np.int64), num // dd)
