@@ -429,25 +429,21 @@ struct FeatVis {
   }
 };
 
-// One block = 4 tiles x 16 probe rays at pixel (16 tx + 4 a + 2, 16 ty + 4 b + 2)
-// (clamped to the image), walked with the tree truncated at level lc.  Two
-// waves walk the two spans of every probe ray (span_setup) and wave 0 adds
-// the second span's statistics to its own, so long probes do not hold the
-// launch; the statistics are sums over cells, so the split changes only
-// their rounding.
-constexpr int kFeatStats = 15;  // col, len, slg, slg2, hist[10], segments
-__global__ __launch_bounds__(128) void k_features(TreeView T, CameraView C, int lc, int tiles_x, int tiles_y,
-                                                  float foot_log2, uint16_t* __restrict__ feat,
-                                                  unsigned long long* __restrict__ zero_stats,
-                                                  unsigned long long* __restrict__ zero_slots) {
-  __shared__ float part[kFeatStats * 64];
+// One block = one wave = 4 tiles x 16 probe rays at pixel (16 tx + 4 a + 2,
+// 16 ty + 4 b + 2) (clamped to the image), each ray walked whole with the
+// tree truncated at level lc (probes are short at a coarse level, so a
+// split into spans would only repeat the ray set-up).
+__global__ __launch_bounds__(64) void k_features(TreeView T, CameraView C, int lc, int tiles_x, int tiles_y,
+                                                 float foot_log2, uint16_t* __restrict__ feat,
+                                                 unsigned long long* __restrict__ zero_stats,
+                                                 unsigned long long* __restrict__ zero_slots) {
   // the LOD render's statistics and counter slots start from zero here (the
   // plan and the repair add to them later on the stream)
   if (zero_stats && blockIdx.x == 0) {
     if (threadIdx.x < 8) zero_stats[threadIdx.x] = 0;
     for (int e = (int)threadIdx.x; e < kStatSlots * kSlotU64; e += (int)blockDim.x) zero_slots[e] = 0;
   }
-  const int lane = threadIdx.x & 63, w = (int)(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const int tile = blockIdx.x * 4 + (lane >> 4), probe = lane & 15;
   const int ntiles = tiles_x * tiles_y;
   const int tt = tile < ntiles ? tile : ntiles - 1;
@@ -462,29 +458,11 @@ __global__ __launch_bounds__(128) void k_features(TreeView T, CameraView C, int 
   Ray R;
   Entry E;
   int32_t nseg = 0;
-  const int b0 = T.base < lc ? T.base : lc;
   const bool hit = setup_ray(C, i, j, R, E);
-  if (hit && span_setup(R, E, b0, 2, w))
-    nseg = w == 1 ? walk_fast<FeatVis, true>(T, R, E, lc, v) : walk_fast(T, R, E, lc, v);  // span 1 runs to the box
+  if (hit) nseg = walk_fast<FeatVis, true>(T, R, E, lc, v);  // the whole ray, to the box
   constexpr float kLog10_2 = 0.30102999566398120f;
   v.slg *= kLog10_2;
   v.slg2 *= kLog10_2 * kLog10_2;
-  if (w == 1) {
-    part[0 * 64 + lane] = v.col;
-    part[1 * 64 + lane] = v.len;
-    part[2 * 64 + lane] = v.slg;
-    part[3 * 64 + lane] = v.slg2;
-    for (int c = 0; c < kBins; ++c) part[(4 + c) * 64 + lane] = v.hist[c];
-    part[14 * 64 + lane] = (float)nseg;
-  }
-  __syncthreads();
-  if (w == 1) return;
-  v.col += part[0 * 64 + lane];
-  v.len += part[1 * 64 + lane];
-  v.slg += part[2 * 64 + lane];
-  v.slg2 += part[3 * 64 + lane];
-  for (int c = 0; c < kBins; ++c) v.hist[c] += part[(4 + c) * 64 + lane];
-  nseg += (int32_t)part[14 * 64 + lane];
   // reduce over the 16 probes of the tile
   float cmax = v.col;
   float s[15];
@@ -907,7 +885,7 @@ amr_status launch_features(const amr_tree* t, const amr_camera* cam, int32_t coa
   const double foot = cam->kind == 0 ? 2.0 * std::sqrt(step / fl) : 2.0 * std::sqrt(step) * 0x1.0p-28;
   const float fl2 = (float)std::log2(foot * std::ldexp(1.0, coarse_level) + 1e-30);
   const int ntiles = tx * ty;
-  hipLaunchKernelGGL(k_features, dim3((ntiles + 3) / 4), dim3(128), 0, (hipStream_t)s, t->view, camera_view(*cam),
+  hipLaunchKernelGGL(k_features, dim3((ntiles + 3) / 4), dim3(64), 0, (hipStream_t)s, t->view, camera_view(*cam),
                      coarse_level, tx, ty, fl2, feat, zero_stats, zero_slots);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? AMR_OK : fail(AMR_EHIP, hipGetErrorString(e));
