@@ -94,6 +94,45 @@ __device__ inline f32x4 block_lds_x_wt(const uint16_t* A, int lda, const uint16_
   return acc;
 }
 
+// ------------------------------------------------- lane exchange (DPP)
+// x from another lane of the same 16-lane row, by a DPP move (a VALU
+// operation, no trip through LDS); lanes without a source read 0.
+template <int kCtrl>
+__device__ inline float dpp_f32(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), kCtrl, 0xF, 0xF, false));
+}
+// DPP controls: quad_perm [1,0,3,2] and [2,3,0,1] pair lanes l ^ 1 and l ^ 2;
+// row_half_mirror pairs l with 7 - l inside each 8 lanes, row_mirror l with
+// 15 - l.  After the two quad steps every lane of a quad holds the same
+// value, and after the half mirror every lane of an 8-lane half, so each
+// level pairs the same two partial results as an xor butterfly would: the
+// reductions below give every lane of the row the same value, bit for bit
+// that of the butterfly (addition and max are commutative).
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+__device__ inline float row16_sum(float x) {
+  x += dpp_f32<kDppXor1>(x);
+  x += dpp_f32<kDppXor2>(x);
+  x += dpp_f32<kDppHalfMirror>(x);
+  x += dpp_f32<kDppMirror>(x);
+  return x;
+}
+__device__ inline float row16_max(float x) {
+  x = fmaxf(x, dpp_f32<kDppXor1>(x));
+  x = fmaxf(x, dpp_f32<kDppXor2>(x));
+  x = fmaxf(x, dpp_f32<kDppHalfMirror>(x));
+  x = fmaxf(x, dpp_f32<kDppMirror>(x));
+  return x;
+}
+// Inclusive prefix sum over the lanes of a row (row_shr by 1, 2, 4, 8: lane
+// r adds lane r - d, or 0 below d).
+__device__ inline float row16_scan(float x) {
+  x += dpp_f32<0x111>(x);
+  x += dpp_f32<0x112>(x);
+  x += dpp_f32<0x114>(x);
+  x += dpp_f32<0x118>(x);
+  return x;
+}
+
 // ------------------------------------------------------------------ plan
 // SplitMix64 finaliser (Steele, Lea and Flood, 2014), high 32 bits: the
 // audited-tile selection.
@@ -119,23 +158,16 @@ struct PlanArgs {
 // a lane group, lane r holding class r (zc): the first class whose
 // cumulative softmax probability reaches q, or full depth when the top
 // probability is below the confidence threshold.  Max, sum and the
-// cumulative sum are lane-group reductions and a scan (their rounding order
-// is that of the shuffles); every lane of the group returns the same level.
-__device__ inline int plan_group(float zc, int r, int64_t t, const PlanArgs& A, bool& fallback) {
+// cumulative sum are reductions and a scan inside the 16-lane row (DPP);
+// every lane of the group returns the same level.
+__device__ inline int plan_group(float zc, int64_t t, const PlanArgs& A, bool& fallback) {
   static_assert(kCls == 16, "one class per lane of a 16-lane group");
-  float m = zc;
-  for (int off = 8; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 16));
+  const float m = row16_max(zc);
   const float e = expf(zc - m);
-  float sum = e;
-  for (int off = 8; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 16);
+  const float sum = row16_sum(e);
   const float pc = e / sum;
-  float pmax = pc;
-  for (int off = 8; off > 0; off >>= 1) pmax = fmaxf(pmax, __shfl_xor(pmax, off, 16));
-  float cdf = pc;  // inclusive scan over the classes
-  for (int d = 1; d < 16; d <<= 1) {
-    const float o = __shfl_up(cdf, d, 16);
-    if (r >= d) cdf += o;
-  }
+  const float pmax = row16_max(pc);
+  const float cdf = row16_scan(pc);  // inclusive scan over the classes
   const unsigned long long hit = __ballot(cdf >= A.q);
   const unsigned grp = (unsigned)(hit >> (threadIdx.x & 48)) & 0xFFFFu;  // this lane group's classes
   int L = kLv0 + (grp ? __ffs(grp) - 1 : kCls - 1);
@@ -234,7 +266,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void k_fwd(const uint16_t* __restri
   const int64_t row = r0 + g * 4 + v;
   const int64_t tr = row < n ? row : n - 1;  // rows past n plan a copy and store nothing
   bool fb;
-  const int L = plan_group(z, r, tr, plan, fb);
+  const int L = plan_group(z, tr, plan, fb);
   unsigned long long nv = 0, nf = 0, na = 0, lsum = 0;  // counted by lane r = 0 of each group
   if (r == 0 && row < n) {
     const bool au = audit_draw(row, plan);
@@ -472,12 +504,9 @@ __global__ __launch_bounds__(64) void k_features(TreeView T, CameraView C, int l
   s[3] = v.slg2;
   s[4] = hit ? 1.f : 0.f;
   for (int c = 0; c < kBins; ++c) s[5 + c] = v.hist[c];
-  float segs = (float)nseg;
-  for (int m = 1; m < 16; m <<= 1) {
-    for (int q = 0; q < 15; ++q) s[q] += __shfl_xor(s[q], m, 64);
-    segs += __shfl_xor(segs, m, 64);
-    cmax = fmaxf(cmax, __shfl_xor(cmax, m, 64));
-  }
+  for (int q = 0; q < 15; ++q) s[q] = row16_sum(s[q]);
+  const float segs = row16_sum((float)nseg);
+  cmax = row16_max(cmax);
   if (tile >= ntiles) return;
   const float mean_col = s[0] / 16.f;
   const float L = s[1];
