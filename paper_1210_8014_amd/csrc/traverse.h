@@ -702,7 +702,10 @@ struct MaxVis {
   AMR_HD void seg(int32_t, int, float, int32_t, int32_t, int32_t) { m = fmaxf(m, x); }
 };
 
-struct WMeanVis {
+// kPackedLos: the caller guarantees the interleaved records (pk) and the
+// line-of-sight velocity (los), so neither is tested per cell.
+template <bool kPackedLos = false>
+struct WMeanVisT {
   static constexpr bool kNeedsLength = true;
   const float AMR_GLOBAL* w;
   const float AMR_GLOBAL* f0;
@@ -714,7 +717,7 @@ struct WMeanVis {
   float sw = 0.0f, cw = 0.0f, sf = 0.0f, cf = 0.0f;
   float xw = 0.0f, x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
   AMR_HD void fetch(int32_t node) {
-    if (pk) {
+    if (kPackedLos || pk) {
       const Cell4 q = pk[(uint32_t)node];
       xw = q.f0;
       x0 = q.f1;
@@ -735,11 +738,18 @@ struct WMeanVis {
     float f = x0;
     // line-of-sight velocity v . d^, as fused multiply-adds (correctly
     // rounded on host and device alike)
-    if (los) f = fmaf(x2, dh[2], fmaf(x1, dh[1], x0 * dh[0]));
+    if (kPackedLos || los) f = fmaf(x2, dh[2], fmaf(x1, dh[1], x0 * dh[0]));
     kahan_add(sw, cw, wl);
     kahan_add(sf, cf, wl * f);
   }
 };
+using WMeanVis = WMeanVisT<false>;
+
+// Whether a wmean render takes the interleaved-record path: weight = field
+// 0, line-of-sight velocity of fields 1..3, records built.
+AMR_HD bool packed_los(const TreeView& T, int field, int wfield, int los) {
+  return los && wfield == 0 && field == 1 && T.packed;
+}
 
 struct CountVis {
   static constexpr bool kNeedsLength = false;
@@ -804,7 +814,7 @@ AMR_HD void render_pixel(const TreeView& T, const CameraView& C, int field, int 
     v.f1 = los ? v.f0 + nc : v.f0;
     v.f2 = los ? v.f0 + 2 * nc : v.f0;
     v.los = los;
-    if (los && wfield == 0 && field == 1 && T.packed) v.pk = T.packed;
+    if (packed_los(T, field, wfield, los)) v.pk = T.packed;
     v.dh[0] = v.dh[1] = v.dh[2] = 0.0f;
     if (hit) {
       const float n = sqrtf((float)(R.d64[0] * R.d64[0] + R.d64[1] * R.d64[1] + R.d64[2] * R.d64[2]));
@@ -974,7 +984,8 @@ AMR_HD void take_cut(const V& v, bool* cut) {
 
 // kWholeBox: the span is the whole ray (no stop plane inside the box).
 // kCut: *cut receives whether the walk cut a cell (TracksCut).
-template <int OP, bool kWholeBox = false, bool kCut = false>
+// kPackedLos (wmean): the caller guarantees packed_los().
+template <int OP, bool kWholeBox = false, bool kCut = false, bool kPackedLos = false>
 AMR_HD void walk_span(const TreeView& T, const Ray& R, Entry& E, int max_level, int field, int wfield, int los,
                       Partial& P, bool* cut = nullptr) {
   const int64_t nc = T.ncells;
@@ -995,13 +1006,13 @@ AMR_HD void walk_span(const TreeView& T, const Ray& R, Entry& E, int max_level, 
     P.s0 = v.m;
     take_cut(v, cut);
   } else {
-    CutIf<kCut, WMeanVis> v;
+    CutIf<kCut, WMeanVisT<kPackedLos>> v;
     v.w = T.val + (int64_t)wfield * nc;
     v.f0 = T.val + (int64_t)field * nc;
     v.f1 = los ? v.f0 + nc : v.f0;
     v.f2 = los ? v.f0 + 2 * nc : v.f0;
     v.los = los;
-    if (los && wfield == 0 && field == 1 && T.packed) v.pk = T.packed;
+    if (kPackedLos || packed_los(T, field, wfield, los)) v.pk = T.packed;
     const float n = sqrtf((float)(R.d64[0] * R.d64[0] + R.d64[1] * R.d64[1] + R.d64[2] * R.d64[2]));
     AMR_UNROLL
     for (int k = 0; k < 3; ++k) v.dh[k] = (float)R.d64[k] / n;
