@@ -82,12 +82,12 @@ def lod_leg(seed: int = 100):
 
 def batch_kernel_name(config: str, op: str) -> str:
     """Name of the kernel a batch launch shape runs for op on this workload
-    (as rocprofv3 shows it); wmean here is the line-of-sight velocity weighted
-    by density, which takes the interleaved-record walk."""
+    (as rocprofv3 shows it).  Both ops here have the common field layout
+    (sum of density; line-of-sight velocity weighted by density on the
+    interleaved records), so the grid shapes run their specialised walk."""
     code = {"sum": 0, "max": 1, "wmean": 2}[op]
     if "grid" in config:
-        return "k_batch_grid<%d, %d, %s>" % (code, 2 if "split2" in config else 1,
-                                             "true" if op == "wmean" else "false")
+        return "k_batch_grid<%d, %d, true>" % (code, 2 if "split2" in config else 1)
     return "k_batch<%d, ...> (%s)" % (code, config)
 
 

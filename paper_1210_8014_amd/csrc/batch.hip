@@ -94,8 +94,8 @@ __global__ __launch_bounds__(64) void k_batch(const BatchImage* __restrict__ img
 
 // One block per packet of all images (images largest first, so the long
 // pieces start early); K waves walk the K spans of each ray and merge in LDS.
-// PL (wmean): every image takes the interleaved-record line-of-sight path.
-template <int OP, int K, bool PL = false>
+// STD: every image has the op's common field layout (std_fields).
+template <int OP, int K, bool STD = false>
 __global__ __launch_bounds__(64 * K) void k_batch_grid(const BatchImage* __restrict__ imgs,
                                                       const int64_t* __restrict__ begin, int32_t nimg) {
   __shared__ float part[(K > 1 ? K - 1 : 1) * 4 * 64];
@@ -119,9 +119,9 @@ __global__ __launch_bounds__(64 * K) void k_batch_grid(const BatchImage* __restr
   if (in && setup_ray(I.c, i, j, R, E) && span_setup(R, E, b0, K, w)) {
     // the last span (the whole ray when K = 1) runs to the box: one-comparison end test
     if (K == 1 || w == K - 1)
-      walk_span<OP, true, false, PL>(I.t, R, E, I.max_level, I.field, I.wfield, I.los, P);
+      walk_span<OP, true, false, STD>(I.t, R, E, I.max_level, I.field, I.wfield, I.los, P);
     else
-      walk_span<OP, false, false, PL>(I.t, R, E, I.max_level, I.field, I.wfield, I.los, P);
+      walk_span<OP, false, false, STD>(I.t, R, E, I.max_level, I.field, I.wfield, I.los, P);
   }
   if (K > 1) {
     if (w > 0) {
@@ -171,10 +171,10 @@ __global__ void k_zero_counter(unsigned long long* c) {
 
 template <int OP>
 hipError_t launch_batch_op(const BatchConfig& cfg, const BatchImage* imgs, const int64_t* begin, int nimg,
-                           int64_t total, unsigned long long* counter, int grid, bool packed, hipStream_t s) {
-  if (OP == kOpWMean && packed && cfg.split == 2)
+                           int64_t total, unsigned long long* counter, int grid, bool std_layout, hipStream_t s) {
+  if (std_layout && cfg.split == 2)
     hipLaunchKernelGGL((k_batch_grid<OP, 2, true>), dim3((unsigned)total), dim3(128), 0, s, imgs, begin, nimg);
-  else if (OP == kOpWMean && packed && cfg.split == 1)
+  else if (std_layout && cfg.split == 1)
     hipLaunchKernelGGL((k_batch_grid<OP, 1, true>), dim3((unsigned)total), dim3(64), 0, s, imgs, begin, nimg);
   else if (cfg.split == 2)
     hipLaunchKernelGGL((k_batch_grid<OP, 2>), dim3((unsigned)total), dim3(128), 0, s, imgs, begin, nimg);
@@ -264,14 +264,15 @@ struct amr_batch {
     hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, s, d_counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // the specialised wmean walk when every image takes the interleaved-record path
-    bool pl = true;
-    for (const BatchImage& I : host_images) pl = pl && packed_los(I.t, I.field, I.wfield, I.los);
+    // the specialised walk when every image has the op's common field layout
+    const int o = op == AMR_SUM ? kOpSum : op == AMR_MAX ? kOpMax : kOpWMean;
+    bool sl = true;
+    for (const BatchImage& I : host_images) sl = sl && std_fields(o, I.t, I.field, I.wfield, I.los);
     if (op == AMR_SUM)
-      return launch_batch_op<kOpSum>(cfg, d_imgs, d_begin, nimg, total_packets, d_counter, grid, false, s);
+      return launch_batch_op<kOpSum>(cfg, d_imgs, d_begin, nimg, total_packets, d_counter, grid, sl, s);
     if (op == AMR_MAX)
-      return launch_batch_op<kOpMax>(cfg, d_imgs, d_begin, nimg, total_packets, d_counter, grid, false, s);
-    return launch_batch_op<kOpWMean>(cfg, d_imgs, d_begin, nimg, total_packets, d_counter, grid, pl, s);
+      return launch_batch_op<kOpMax>(cfg, d_imgs, d_begin, nimg, total_packets, d_counter, grid, sl, s);
+    return launch_batch_op<kOpWMean>(cfg, d_imgs, d_begin, nimg, total_packets, d_counter, grid, sl, s);
   }
   hipError_t capture() {
     drop_graph();

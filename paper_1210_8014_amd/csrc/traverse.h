@@ -681,26 +681,31 @@ AMR_HD int32_t walk_ray(const TreeView& T, const Ray& R, Entry& E, int max_level
 
 // ----------------------------------------------------------------- visitors
 
-struct SumVis {
+// kField0: the caller guarantees field0 (no per-cell test).
+template <bool kField0 = false>
+struct SumVisT {
   static constexpr bool kNeedsLength = true;
   const float AMR_GLOBAL* v;
   bool field0 = false;  // v is field 0: the fast walk hands over the value
   float s = 0.0f, c = 0.0f, x = 0.0f;
   AMR_HD void fetch(int32_t node) { x = v[(uint32_t)node]; }
-  AMR_HD void fetch0(int32_t node, float v0) { x = field0 ? v0 : v[(uint32_t)node]; }
+  AMR_HD void fetch0(int32_t node, float v0) { x = (kField0 || field0) ? v0 : v[(uint32_t)node]; }
   AMR_HD void seg(int32_t, int, float len, int32_t, int32_t, int32_t) { kahan_add(s, c, x * len); }
 };
+using SumVis = SumVisT<false>;
 
-struct MaxVis {
+template <bool kField0 = false>
+struct MaxVisT {
   static constexpr bool kNeedsLength = false;
   const float AMR_GLOBAL* v;
   float m;
   bool field0 = false;
   float x = 0.0f;
   AMR_HD void fetch(int32_t node) { x = v[(uint32_t)node]; }
-  AMR_HD void fetch0(int32_t node, float v0) { x = field0 ? v0 : v[(uint32_t)node]; }
+  AMR_HD void fetch0(int32_t node, float v0) { x = (kField0 || field0) ? v0 : v[(uint32_t)node]; }
   AMR_HD void seg(int32_t, int, float, int32_t, int32_t, int32_t) { m = fmaxf(m, x); }
 };
+using MaxVis = MaxVisT<false>;
 
 // kPackedLos: the caller guarantees the interleaved records (pk) and the
 // line-of-sight velocity (los), so neither is tested per cell.
@@ -751,6 +756,7 @@ AMR_HD bool packed_los(const TreeView& T, int field, int wfield, int los) {
   return los && wfield == 0 && field == 1 && T.packed;
 }
 
+
 struct CountVis {
   static constexpr bool kNeedsLength = false;
   AMR_HD void fetch(int32_t) {}
@@ -778,6 +784,12 @@ struct TraceVis {
 // ------------------------------------------------------------ one pixel
 
 enum { kOpSum = 0, kOpMax = 1, kOpWMean = 2 };
+
+// The common field layout of an op: sum and max of field 0 (the value the
+// fast walk already holds), wmean on the interleaved-record path.
+AMR_HD bool std_fields(int op, const TreeView& T, int field, int wfield, int los) {
+  return op == kOpWMean ? packed_los(T, field, wfield, los) : field == 0;
+}
 
 // The whole per-pixel computation of one projection; out receives the
 // pixel value, aux (WMEAN) the weight integral.
@@ -984,13 +996,13 @@ AMR_HD void take_cut(const V& v, bool* cut) {
 
 // kWholeBox: the span is the whole ray (no stop plane inside the box).
 // kCut: *cut receives whether the walk cut a cell (TracksCut).
-// kPackedLos (wmean): the caller guarantees packed_los().
-template <int OP, bool kWholeBox = false, bool kCut = false, bool kPackedLos = false>
+// kStd: the caller guarantees std_fields() (no per-cell tests of the layout).
+template <int OP, bool kWholeBox = false, bool kCut = false, bool kStd = false>
 AMR_HD void walk_span(const TreeView& T, const Ray& R, Entry& E, int max_level, int field, int wfield, int los,
                       Partial& P, bool* cut = nullptr) {
   const int64_t nc = T.ncells;
   if (OP == kOpSum) {
-    CutIf<kCut, SumVis> v;
+    CutIf<kCut, SumVisT<kStd>> v;
     v.v = T.val + (int64_t)field * nc;
     v.field0 = field == 0;
     walk_fast<decltype(v), kWholeBox>(T, R, E, max_level, v);
@@ -998,7 +1010,7 @@ AMR_HD void walk_span(const TreeView& T, const Ray& R, Entry& E, int max_level, 
     P.c0 = v.c;
     take_cut(v, cut);
   } else if (OP == kOpMax) {
-    CutIf<kCut, MaxVis> v;
+    CutIf<kCut, MaxVisT<kStd>> v;
     v.v = T.val + (int64_t)field * nc;
     v.m = -INFINITY;
     v.field0 = field == 0;
@@ -1006,13 +1018,13 @@ AMR_HD void walk_span(const TreeView& T, const Ray& R, Entry& E, int max_level, 
     P.s0 = v.m;
     take_cut(v, cut);
   } else {
-    CutIf<kCut, WMeanVisT<kPackedLos>> v;
+    CutIf<kCut, WMeanVisT<kStd>> v;
     v.w = T.val + (int64_t)wfield * nc;
     v.f0 = T.val + (int64_t)field * nc;
     v.f1 = los ? v.f0 + nc : v.f0;
     v.f2 = los ? v.f0 + 2 * nc : v.f0;
     v.los = los;
-    if (kPackedLos || packed_los(T, field, wfield, los)) v.pk = T.packed;
+    if (kStd || packed_los(T, field, wfield, los)) v.pk = T.packed;
     const float n = sqrtf((float)(R.d64[0] * R.d64[0] + R.d64[1] * R.d64[1] + R.d64[2] * R.d64[2]));
     AMR_UNROLL
     for (int k = 0; k < 3; ++k) v.dh[k] = (float)R.d64[k] / n;

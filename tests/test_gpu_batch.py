@@ -32,18 +32,22 @@ def _mixed_batch():
     return trees, cams, pairs
 
 
-@pytest.mark.parametrize("op", ["sum", "max", "wmean"])
+@pytest.mark.parametrize("op", ["sum", "max", "wmean", "sum_field1", "wmean_los"])
 def test_batch_matches_single_renders_on_every_replay(op):
+    """sum and max of field 0 and wmean with the line of sight on the
+    interleaved records run the grid kernels specialised for that layout;
+    sum of field 1 and wmean of a scalar field run the general ones."""
     import paper_1210_8014_amd as amr
 
     trees, cams, pairs = _mixed_batch()
-    o = {"sum": amr.SUM, "max": amr.MAX, "wmean": amr.WMEAN}[op]
-    kw = dict(field=0) if op != "wmean" else dict(field=1, weight=0, los=False)
-    if op == "wmean":
-        # tiny has one field: use density-weighted density there is not possible; restrict to disks
+    o = {"sum": amr.SUM, "max": amr.MAX, "wmean": amr.WMEAN, "sum_field1": amr.SUM, "wmean_los": amr.WMEAN}[op]
+    kw = {"sum": dict(field=0), "max": dict(field=0), "sum_field1": dict(field=1),
+          "wmean": dict(field=1, weight=0, los=False), "wmean_los": dict(field=1, weight=0, los=True)}[op]
+    if op in ("wmean", "sum_field1", "wmean_los"):
+        # tiny has one field: restrict to the disks (four fields)
         pairs = [p for p in pairs if p[0] > 0]
     outs = [torch.full((cams[c].W * cams[c].H,), -7.0, device="cuda") for _, c in pairs]
-    auxs = [torch.full_like(x, -7.0) for x in outs] if op == "wmean" else None
+    auxs = [torch.full_like(x, -7.0) for x in outs] if o == amr.WMEAN else None
     B = amr.Batch(trees, cams, pairs, o, outs, auxs, **kw)
     split_variant = amr.variants().index("p8x8_split2_fast")
 
@@ -51,7 +55,7 @@ def test_batch_matches_single_renders_on_every_replay(op):
         out = []
         for (t, c) in pairs:
             r = torch.empty(cams[c].W * cams[c].H, device="cuda")
-            a = torch.empty_like(r) if op == "wmean" else None
+            a = torch.empty_like(r) if o == amr.WMEAN else None
             amr.render(trees[t], cams[c], o, r, a, variant=variant, **kw)
             out.append((r, a))
         return out
