@@ -503,7 +503,8 @@ struct TracksCut<V, decltype((void)V::kTrackCut)> {
   static constexpr bool value = V::kTrackCut;
 };
 
-template <class Vis, bool kWholeBox = false>
+// kShallow: the caller guarantees max_level < kDeepLevel (no fp64 chords).
+template <class Vis, bool kWholeBox = false, bool kShallow = false>
 AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_level, Vis& vis) {
   const int b0 = T.base < max_level ? T.base : max_level;
   const int sb = kFix - b0;
@@ -609,7 +610,7 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
     if (Vis::kNeedsLength) {
       // (the product of the negated entry numerator is the second one's addend)
       const int64_t N = mul64(nb, E.da) + mul64(-E.en, db);
-      if (max_level < kDeepLevel || lvl < kDeepLevel)
+      if (kShallow || max_level < kDeepLevel || lvl < kDeepLevel)
         len = chord_f32(N, ulen, invb, E.inv_da);
       else
         len = (float)((double)N * R.ulen64 / ((double)E.da * (double)db));
@@ -996,7 +997,10 @@ AMR_HD void take_cut(const V& v, bool* cut) {
 
 // kWholeBox: the span is the whole ray (no stop plane inside the box).
 // kCut: *cut receives whether the walk cut a cell (TracksCut).
-// kStd: the caller guarantees std_fields() (no per-cell tests of the layout).
+// kStd: the caller guarantees std_fields(), and for sum and max also
+// max_level < kDeepLevel (no per-cell tests of the layout, nor for sum and
+// max of the chord precision; measured, the wmean walk is faster with that
+// test kept).
 template <int OP, bool kWholeBox = false, bool kCut = false, bool kStd = false>
 AMR_HD void walk_span(const TreeView& T, const Ray& R, Entry& E, int max_level, int field, int wfield, int los,
                       Partial& P, bool* cut = nullptr) {
@@ -1005,7 +1009,7 @@ AMR_HD void walk_span(const TreeView& T, const Ray& R, Entry& E, int max_level, 
     CutIf<kCut, SumVisT<kStd>> v;
     v.v = T.val + (int64_t)field * nc;
     v.field0 = field == 0;
-    walk_fast<decltype(v), kWholeBox>(T, R, E, max_level, v);
+    walk_fast<decltype(v), kWholeBox, kStd>(T, R, E, max_level, v);
     P.s0 = v.s;
     P.c0 = v.c;
     take_cut(v, cut);
@@ -1014,7 +1018,7 @@ AMR_HD void walk_span(const TreeView& T, const Ray& R, Entry& E, int max_level, 
     v.v = T.val + (int64_t)field * nc;
     v.m = -INFINITY;
     v.field0 = field == 0;
-    walk_fast<decltype(v), kWholeBox>(T, R, E, max_level, v);
+    walk_fast<decltype(v), kWholeBox, kStd>(T, R, E, max_level, v);
     P.s0 = v.m;
     take_cut(v, cut);
   } else {
