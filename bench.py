@@ -48,7 +48,9 @@ def kernel_name(variant: int, op: str) -> str:
     name = amr.variants()[variant if variant >= 0 else amr.default_variant()]
     code = {"sum": 0, "max": 1, "wmean": 2}[op]
     if "split" in name:
-        return "k_render_split<%d, %s>" % (code, name.split("split")[1].split("_")[0])
+        remap = 2 if name.endswith("center") else (1 if name.endswith("xcdband") else 0)
+        # both ops of this workload have the common field layout: the specialised walk
+        return "k_render_split<%d, %s, %d, true>" % (code, name.split("split")[1].split("_")[0], remap)
     return "k_render<%d, ...> (%s)" % (code, name)
 
 

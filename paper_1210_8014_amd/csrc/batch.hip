@@ -94,8 +94,7 @@ __global__ __launch_bounds__(64) void k_batch(const BatchImage* __restrict__ img
 
 // One block per packet of all images (images largest first, so the long
 // pieces start early); K waves walk the K spans of each ray and merge in LDS.
-// STD: every image has the op's common field layout (std_fields) and, for
-// sum and max, a maximum level below kDeepLevel (walk_span's kStd).
+// STD: every image may take walk_span's kStd walk (std_walk).
 template <int OP, int K, bool STD = false>
 __global__ __launch_bounds__(64 * K) void k_batch_grid(const BatchImage* __restrict__ imgs,
                                                       const int64_t* __restrict__ begin, int32_t nimg) {
@@ -268,8 +267,7 @@ struct amr_batch {
     // the specialised walk when every image has the op's common field layout
     const int o = op == AMR_SUM ? kOpSum : op == AMR_MAX ? kOpMax : kOpWMean;
     bool sl = true;
-    for (const BatchImage& I : host_images)
-      sl = sl && std_fields(o, I.t, I.field, I.wfield, I.los) && (o == kOpWMean || I.max_level < kDeepLevel);
+    for (const BatchImage& I : host_images) sl = sl && std_walk(o, I.t, I.field, I.wfield, I.los, I.max_level);
     if (op == AMR_SUM)
       return launch_batch_op<kOpSum>(cfg, d_imgs, d_begin, nimg, total_packets, d_counter, grid, sl, s);
     if (op == AMR_MAX)

@@ -580,7 +580,7 @@ __global__ __launch_bounds__(64) void k_labels(ImgPtrs I, int W, int H, int tile
 // One walk of a packet's rays with the tree truncated at lw: wave w walks
 // span w of its lane's ray (cut tracking on), wave 1 leaves its partial sums
 // in part for wave 0.
-template <int OP>
+template <int OP, bool STD>
 __device__ __forceinline__ void tile_walk(const RenderArgs& A, int i, int j, bool in, int w, int lw, float* part,
                                           Partial& P, bool& cut) {
   partial_init<OP>(P);
@@ -589,9 +589,9 @@ __device__ __forceinline__ void tile_walk(const RenderArgs& A, int i, int j, boo
   Entry E;
   if (in && setup_ray(A.c, i, j, R, E) && span_setup(R, E, A.t.base < lw ? A.t.base : lw, 2, w)) {
     if (w == 1)  // the last span runs to the box
-      walk_span<OP, true, true>(A.t, R, E, lw, A.field, A.wfield, A.los, P, &cut);
+      walk_span<OP, true, true, STD>(A.t, R, E, lw, A.field, A.wfield, A.los, P, &cut);
     else
-      walk_span<OP, false, true>(A.t, R, E, lw, A.field, A.wfield, A.los, P, &cut);
+      walk_span<OP, false, true, STD>(A.t, R, E, lw, A.field, A.wfield, A.los, P, &cut);
   }
   if (w == 1) {
     float* q = part + (threadIdx.x & 63);
@@ -611,7 +611,8 @@ __device__ __forceinline__ void tile_finish(const float* part, Partial& P, float
   partial_finish<OP>(P, o, x);
 }
 
-template <int OP>
+// STD: the render may take walk_span's kStd walk (std_walk).
+template <int OP, bool STD = false>
 __global__ __launch_bounds__(128, OP == kOpWMean ? 7 : 8) void k_render_tiles(RenderArgs A, const int8_t* __restrict__ level,
                                                       const uint8_t* __restrict__ audit, int tiles_x,
                                                       float* __restrict__ full_out, float* __restrict__ full_aux,
@@ -630,7 +631,7 @@ __global__ __launch_bounds__(128, OP == kOpWMean ? 7 : 8) void k_render_tiles(Re
   Partial P;
   bool cut;
   float o, x;
-  tile_walk<OP>(A, i, j, in, w, L, part, P, cut);
+  tile_walk<OP, STD>(A, i, j, in, w, L, part, P, cut);
   // (also the barrier for part) did a ray of either span cut a cell?
   const bool again = audited ? __syncthreads_or(cut ? 1 : 0) != 0 : (__syncthreads(), false);
   if (w == 0 && in) {
@@ -645,7 +646,7 @@ __global__ __launch_bounds__(128, OP == kOpWMean ? 7 : 8) void k_render_tiles(Re
   if (!again) return;  // block-uniform
   if (threadIdx.x == 0) atomicAdd(&stats[5], 1ull);
   __syncthreads();  // wave 0 has read part before wave 1 writes it again
-  tile_walk<OP>(A, i, j, in, w, A.max_level, part, P, cut);
+  tile_walk<OP, STD>(A, i, j, in, w, A.max_level, part, P, cut);
   __syncthreads();
   if (w == 0 && in) {
     tile_finish<OP>(part, P, o, x);
@@ -1072,19 +1073,33 @@ amr_status amr_render_lod(const amr_tree* t, const amr_camera* cam, amr_op op, c
   float* full_out = (float*)(w + ws_planes_offset(cam->W, cam->H));
   float* full_aux = (float*)((char*)full_out + align256((int64_t)cam->W * cam->H * 4));
   const unsigned rb = (np + kRepairPackets - 1) / kRepairPackets;  // repair blocks
+  const int opc = op == AMR_SUM ? kOpSum : op == AMR_MAX ? kOpMax : kOpWMean;
+  const bool sw = std_walk(opc, a.t, a.field, a.wfield, a.los, a.max_level);  // walk_span's kStd walk
   if (op == AMR_SUM) {
-    hipLaunchKernelGGL(k_render_tiles<kOpSum>, dim3(np), dim3(128), 0, hs, a, lev, aud, tx, full_out, full_aux,
-                       st);
+    if (sw)
+      hipLaunchKernelGGL((k_render_tiles<kOpSum, true>), dim3(np), dim3(128), 0, hs, a, lev, aud, tx, full_out,
+                         full_aux, st);
+    else
+      hipLaunchKernelGGL(k_render_tiles<kOpSum>, dim3(np), dim3(128), 0, hs, a, lev, aud, tx, full_out, full_aux,
+                         st);
     hipLaunchKernelGGL(k_audit_repair<kOpSum>, dim3(rb), dim3(64), 0, hs, a, lev, aud, tx, c.rel_tol, full_out,
                        full_aux, st, slots);
   } else if (op == AMR_MAX) {
-    hipLaunchKernelGGL(k_render_tiles<kOpMax>, dim3(np), dim3(128), 0, hs, a, lev, aud, tx, full_out, full_aux,
-                       st);
+    if (sw)
+      hipLaunchKernelGGL((k_render_tiles<kOpMax, true>), dim3(np), dim3(128), 0, hs, a, lev, aud, tx, full_out,
+                         full_aux, st);
+    else
+      hipLaunchKernelGGL(k_render_tiles<kOpMax>, dim3(np), dim3(128), 0, hs, a, lev, aud, tx, full_out, full_aux,
+                         st);
     hipLaunchKernelGGL(k_audit_repair<kOpMax>, dim3(rb), dim3(64), 0, hs, a, lev, aud, tx, c.rel_tol, full_out,
                        full_aux, st, slots);
   } else {
-    hipLaunchKernelGGL(k_render_tiles<kOpWMean>, dim3(np), dim3(128), 0, hs, a, lev, aud, tx, full_out,
-                       full_aux, st);
+    if (sw)
+      hipLaunchKernelGGL((k_render_tiles<kOpWMean, true>), dim3(np), dim3(128), 0, hs, a, lev, aud, tx, full_out,
+                         full_aux, st);
+    else
+      hipLaunchKernelGGL(k_render_tiles<kOpWMean>, dim3(np), dim3(128), 0, hs, a, lev, aud, tx, full_out,
+                         full_aux, st);
     hipLaunchKernelGGL(k_audit_repair<kOpWMean>, dim3(rb), dim3(64), 0, hs, a, lev, aud, tx, c.rel_tol, full_out,
                        full_aux, st, slots);
   }

@@ -68,7 +68,8 @@ __global__ __launch_bounds__(64 * WPB) void k_render(RenderArgs A) {
 // concurrently on different waves and the longest rays of an image, which
 // bound its time when a lone wave walks them, finish about K times sooner.
 // Partial sums meet in LDS and wave 0 merges them in span order.
-template <int OP, int K, int REMAP>
+// STD: the render may take walk_span's kStd walk (std_walk).
+template <int OP, int K, int REMAP, bool STD = false>
 __global__ __launch_bounds__(64 * K) void k_render_split(RenderArgs A) {
   __shared__ float part[(K - 1) * 4 * 64];
   const int lane = threadIdx.x & 63, w = (int)(threadIdx.x >> 6);
@@ -85,9 +86,9 @@ __global__ __launch_bounds__(64 * K) void k_render_split(RenderArgs A) {
   if (in && setup_ray(A.c, i, j, R, E) && span_setup(R, E, b0, K, w)) {
     // the last span always runs to the box (its one-comparison end test)
     if (w == K - 1)
-      walk_span<OP, true>(A.t, R, E, A.max_level, A.field, A.wfield, A.los, P);
+      walk_span<OP, true, false, STD>(A.t, R, E, A.max_level, A.field, A.wfield, A.los, P);
     else
-      walk_span<OP>(A.t, R, E, A.max_level, A.field, A.wfield, A.los, P);
+      walk_span<OP, false, false, STD>(A.t, R, E, A.max_level, A.field, A.wfield, A.los, P);
   }
   if (w > 0) {
     float* q = part + (w - 1) * 4 * 64 + lane;
@@ -183,7 +184,10 @@ hipError_t launch_one(const RenderArgs& a, hipStream_t s) {
 template <int OP, int K, int REMAP = kRemapNone>
 hipError_t launch_split(const RenderArgs& a, hipStream_t s) {
   const int64_t packets = (int64_t)a.packets_x * a.packets_y;
-  hipLaunchKernelGGL((k_render_split<OP, K, REMAP>), dim3((unsigned)packets), dim3(64 * K), 0, s, a);
+  if (std_walk(OP, a.t, a.field, a.wfield, a.los, a.max_level))
+    hipLaunchKernelGGL((k_render_split<OP, K, REMAP, true>), dim3((unsigned)packets), dim3(64 * K), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_render_split<OP, K, REMAP>), dim3((unsigned)packets), dim3(64 * K), 0, s, a);
   return hipGetLastError();
 }
 

@@ -792,6 +792,12 @@ AMR_HD bool std_fields(int op, const TreeView& T, int field, int wfield, int los
   return op == kOpWMean ? packed_los(T, field, wfield, los) : field == 0;
 }
 
+// Whether a render may use walk_span's kStd walk: the common field layout,
+// and for sum and max a maximum level below kDeepLevel.
+AMR_HD bool std_walk(int op, const TreeView& T, int field, int wfield, int los, int max_level) {
+  return std_fields(op, T, field, wfield, los) && (op == kOpWMean || max_level < kDeepLevel);
+}
+
 // The whole per-pixel computation of one projection; out receives the
 // pixel value, aux (WMEAN) the weight integral.
 // Descent modes: restart at the complete base level (kWalkBase), at the
