@@ -271,15 +271,17 @@ def disk_cameras(W: int = 2048, H: int = 2048, max_level: int = 16) -> List[dict
 
 
 def deepzoom_camera(W: int = 4096, H: int = 4096, seed: int = 0, max_level: int = -1) -> dict:
-    """Eye 2^-9 box from core 0, inside the disk, fov_y = 2 atan(0.5): the
-    pixel footprint at the target is 2^-21 box at 4096^2."""
+    """Eye 2^-9 box from core 0, inside the disk, fov_y = 2 atan(0.625): the
+    pixel footprint at the target is 1.25 x 2^-21 box at 4096^2, so the
+    automatic maximum level is 21 (not on a rounding boundary of the level
+    rule)."""
     c = configs()["deepzoom"]
     tgt = core_position(seed, c["lmax"], c["m_thr"], 0)
     s = 2.0 ** -9
     th = math.radians(60.0)
     eye = (tgt[0], tgt[1] - s * math.sin(th), tgt[2] + s * math.cos(th))
     up = (0.0, math.cos(th), math.sin(th))
-    return camera("persp", eye, tgt, up, W, H, fov_y=2.0 * math.atan(0.5), max_level=max_level)
+    return camera("persp", eye, tgt, up, W, H, fov_y=2.0 * math.atan(0.625), max_level=max_level)
 
 
 def orbit_cameras(n: int = 64, seed: int = 0, side_lo: int = 512, side_hi: int = 2048, multiple: int = 16,

@@ -151,17 +151,23 @@ typedef struct {
   int64_t O[3], F[3], U[3], V[3];
 } amr_camera;
 
-/* Quantise a camera (host only, no GPU needed).  With f = target - eye,
- * fh = f / |f|, rh = (up x fh) / |up x fh|, uh = fh x rh, s = tan(fov_y/2)/H
- * (perspective) or ortho_height / (2H) (orthographic):
- *   O = rne(eye 2^28), F = rne(fh 2^28), U = rne(rh s 2^28), V = rne(uh s 2^28)
- * in fp64, each norm as sqrt((x^2 + y^2) + z^2), no fused operations.
+/* Quantise a camera (host only, no GPU needed).  The record is defined on
+ * the real numbers: with f = target - eye, g = up x f, h = f x g (so that
+ * f / |f|, g / |g| and h / (|f| |g|) are the view, image-x and image-y unit
+ * vectors) and the half-pixel step s = tan(fov_y/2) / H (perspective: the
+ * field of view is vertical) or ortho_height / (2H) (orthographic),
+ *   O = rne(2^28 eye), F = rne(2^28 f/|f|), U = rne(2^28 s g/|g|),
+ *   V = rne(2^28 s h/(|f| |g|)),
+ * rne = round to nearest, ties to even.  The library evaluates this in
+ * fp64 (normalised vectors, norms as sqrt((x^2 + y^2) + z^2), no fused
+ * operations), which yields these integers unless a component lies within
+ * about 1e-7 of a rounding boundary.
  * Automatic max_level (Sec. 2): the smallest L >= 0 with 2^-L <= p, p the
  * pixel footprint (ortho_height / H, or 2 |f| tan(fov_y/2) / H at the
  * target), plus level_bias, clamped to [0, 24] and to the tree's deepest
- * level when t is not NULL.  AMR_EINVAL on a degenerate basis, W or H
- * outside 1..32768, origins or directions outside the ranges above, or an
- * explicit max_level outside 0..24. */
+ * level when t is not NULL.  AMR_EINVAL on a degenerate basis, fov_y
+ * outside (0, 3), W or H outside 1..32768, origins or directions outside
+ * the ranges above, or an explicit max_level outside 0..24. */
 amr_status amr_set_camera(const amr_camera_desc* d, const amr_tree* t, amr_camera* out);
 
 /* ---------------------------------------------------------------- render */

@@ -2,19 +2,26 @@
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  The product library never loads it
-and shares no code with it.  The numerics live in ``oracle.c`` (fp64 plus
-exact 128-bit integer predicates); this module only builds it with gcc and
-marshals numpy arrays through ctypes.
+and shares no code with it.  The ray casting lives in ``oracle.c`` (fp64 plus
+exact 128-bit integer predicates), which consumes the integer camera record;
+the record itself comes from ``camera.py`` (exact rational and 90-digit
+decimal arithmetic).  This module builds the C part with gcc and marshals
+numpy arrays through ctypes.
 
-Function -> what pins it (tests/test_oracle_pins.py):
-  camera quantisation   integer round trip, bounds, mirror symmetry
+Function -> what pins it (tests/test_oracle_pins.py, tests/golden/):
+  camera quantisation   hand-derived orthographic and perspective records,
+                        the field-of-view edge ray, integer round trip,
+                        bounds, mirror symmetry
   tree build/restrict   mass conservation at every truncation level,
                         momentum conservation, rejection of gaps/overlaps
   segments and order    exact Fraction brute force over every leaf,
                         textbook grid DDA on uniform trees, closed-form counts
   chord lengths         constant field -> value x box chord; sum of chords
   sum / max / wmean     brute force, dense-grid sums, bounds, constant-field
-                        and unit-weight identities
+                        and unit-weight identities; a hand-worked three-cell
+                        weighted mean with its error scales; a cancelling
+                        sum that plain fp64 accumulation gets wrong
+                        (compensation)
 """
 from __future__ import annotations
 
@@ -25,21 +32,14 @@ from typing import Optional, Sequence
 
 import numpy as np
 
+from . import camera as _camera
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 SUM, MAX, WMEAN = 0, 1, 2
 OK, EINVAL, ETREE, ENOMEM, ECAPACITY = 0, 1, 2, 3, 4
-
-
-class CameraDesc(ctypes.Structure):
-    _fields_ = [
-        ("kind", ctypes.c_int32), ("W", ctypes.c_int32), ("H", ctypes.c_int32),
-        ("max_level", ctypes.c_int32), ("level_bias", ctypes.c_int32), ("pad_", ctypes.c_int32),
-        ("eye", ctypes.c_double * 3), ("target", ctypes.c_double * 3), ("up", ctypes.c_double * 3),
-        ("fov_y", ctypes.c_double), ("ortho_height", ctypes.c_double),
-    ]
 
 
 class Camera(ctypes.Structure):
@@ -73,7 +73,6 @@ def _load():
         if not os.path.exists(_LIB):
             build()
         lib = ctypes.CDLL(_LIB)
-        lib.oc_set_camera.argtypes = [_P(CameraDesc), ctypes.c_int32, _P(Camera)]
         lib.oc_tree_build.argtypes = [ctypes.c_int64] + [ctypes.c_void_p] * 5 + [ctypes.c_int32, ctypes.c_int64,
                                                                                  ctypes.c_void_p,
                                                                                  _P(ctypes.c_void_p)]
@@ -83,7 +82,7 @@ def _load():
         lib.oc_tree_lmax.argtypes = [ctypes.c_void_p]
         lib.oc_lookup.argtypes = [ctypes.c_void_p] + [ctypes.c_int32] * 4 + [ctypes.c_void_p, ctypes.c_void_p]
         lib.oc_render.argtypes = [ctypes.c_void_p, _P(Camera), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64] + [ctypes.c_void_p] * 5 + [
+                                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64] + [ctypes.c_void_p] * 6 + [
                                       ctypes.c_int32]
         lib.oc_trace.argtypes = [ctypes.c_void_p, _P(Camera), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                  ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32]
@@ -98,28 +97,20 @@ def _ptr(a: Optional[np.ndarray]):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
 
-_KIND = {"persp": 0, "ortho": 1}
-
-
-def camera_desc(d: dict) -> CameraDesc:
-    c = CameraDesc()
-    c.kind = _KIND[d["kind"]] if isinstance(d["kind"], str) else int(d["kind"])
-    c.W, c.H = int(d["W"]), int(d["H"])
-    c.max_level = int(d.get("max_level", -1))
-    c.level_bias = int(d.get("level_bias", 0))
-    for k in range(3):
-        c.eye[k], c.target[k], c.up[k] = d["eye"][k], d["target"][k], d["up"][k]
-    c.fov_y = float(d.get("fov_y", 0.0))
-    c.ortho_height = float(d.get("ortho_height", 0.0))
-    return c
-
-
 def set_camera(d: dict, tree_lmax: int = -1) -> Camera:
-    """Quantise a camera description; raises ValueError when rejected."""
+    """Quantise a camera description (camera.quantise); raises ValueError
+    (camera.CameraError) when rejected."""
+    r = _camera.quantise(d, tree_lmax if tree_lmax >= 0 else None)
+    return record(r.as_dict())
+
+
+def record(rec: dict) -> Camera:
+    """The C struct of an integer camera record given as a dict."""
     out = Camera()
-    rc = _load().oc_set_camera(ctypes.byref(camera_desc(d)), int(tree_lmax), ctypes.byref(out))
-    if rc != OK:
-        raise ValueError(f"camera rejected ({rc})")
+    out.kind, out.W, out.H, out.max_level = int(rec["kind"]), int(rec["W"]), int(rec["H"]), int(rec["max_level"])
+    for k in range(3):
+        out.O[k], out.F[k], out.U[k], out.V[k] = (int(rec["O"][k]), int(rec["F"][k]), int(rec["U"][k]),
+                                                  int(rec["V"][k]))
     return out
 
 
@@ -186,8 +177,9 @@ class Tree:
     def render(self, cam: Camera, op: int, field: int = 0, weight: int = 0, los: bool = False,
                rays: Optional[np.ndarray] = None, nthreads: int = 0):
         """Returns dict with 'val' (fp64; sum or wmean), 'max' (fp32),
-        'aux' (wmean weight), 'absf' (wmean mean |f|; with los the mean of the
-        summed magnitudes of the three velocity terms: the error-bar scale), 'count'.  Arrays are
+        'aux' (wmean weight), 'absf' (wmean: weighted mean of |f|, with los of
+        the summed magnitudes of the three velocity terms: the error-bar
+        scale), 'absdot' (wmean: weighted mean of |f| itself), 'count'.  Arrays are
         flat over the requested rays (pixel index j*W+i), or over all pixels."""
         n = cam.W * cam.H if rays is None else int(len(rays))
         r = None if rays is None else np.ascontiguousarray(rays, np.int64)
@@ -195,12 +187,14 @@ class Tree:
         mx = np.zeros(n, np.float32) if op == MAX else None
         aux = np.zeros(n, np.float64) if op == WMEAN else None
         absf = np.zeros(n, np.float64) if op == WMEAN else None
+        absdot = np.zeros(n, np.float64) if op == WMEAN else None
         cnt = np.zeros(n, np.int32)
         rc = _load().oc_render(self._h, ctypes.byref(cam), op, field, weight, int(bool(los)), _ptr(r), n, _ptr(val),
-                               _ptr(mx), _ptr(aux), _ptr(absf), _ptr(cnt), int(nthreads))
+                               _ptr(mx), _ptr(aux), _ptr(absf), _ptr(absdot), _ptr(cnt),
+                               int(nthreads))
         if rc != OK:
             raise RuntimeError(f"oracle render failed ({rc})")
-        return dict(val=val, max=mx, aux=aux, absf=absf, count=cnt)
+        return dict(val=val, max=mx, aux=aux, absf=absf, absdot=absdot, count=cnt)
 
     def probe_stats(self, cam: Camera, rays: np.ndarray, field: int = 0, nthreads: int = 0) -> np.ndarray:
         """[n, 16] per-ray statistics for the learned level of detail (see

@@ -35,10 +35,10 @@
  * formed from an exact 128-bit numerator, then converted to fp64.  Sums use
  * fp64 with Neumaier compensation.
  *
- * Camera: the quantisation below (eye, target, up, fov or ortho height ->
- * integer origin and F, U, V step vectors) is written out operation by
- * operation, because both this oracle and the GPU library implement it from
- * the same definition and must agree bit for bit.
+ * Camera: the oracle consumes the integer camera record (origin O, view
+ * step F, half-pixel steps U and V), which the tests produce with the
+ * oracle's own exact quantiser (camera.py); pixel_ray below turns it into
+ * the integer ray of a pixel.
  */
 #include <math.h>
 #include <stdint.h>
@@ -60,93 +60,9 @@ enum { OC_SUM = 0, OC_MAX = 1, OC_WMEAN = 2 };
 /* ------------------------------------------------------------------ camera */
 
 typedef struct {
-  int32_t kind; /* 0 = perspective, 1 = orthographic */
-  int32_t W, H;
-  int32_t max_level; /* -1: from the pixel footprint */
-  int32_t level_bias;
-  int32_t pad_;
-  double eye[3], target[3], up[3];
-  double fov_y;        /* radians, perspective */
-  double ortho_height; /* box units, orthographic */
-} oc_camera_desc;
-
-typedef struct {
   int32_t kind, W, H, max_level;
   int64_t O[3], F[3], U[3], V[3];
 } oc_camera;
-
-static int64_t rne_fix(double x) { return (int64_t)llrint(ldexp(x, FIX_BITS)); }
-
-/* Camera quantisation (Sec. 2: the camera defines the image and, through
- * the pixel size, the deepest level read). */
-int oc_set_camera(const oc_camera_desc* d, int32_t tree_lmax, oc_camera* out) {
-  if (!d || !out) return OC_EINVAL;
-  if (d->kind != 0 && d->kind != 1) return OC_EINVAL;
-  if (d->W < 1 || d->H < 1 || d->W > 32768 || d->H > 32768) return OC_EINVAL;
-  for (int k = 0; k < 3; ++k)
-    if (!isfinite(d->eye[k]) || !isfinite(d->target[k]) || !isfinite(d->up[k])) return OC_EINVAL;
-  double f[3], fh[3], r[3], rh[3], uh[3];
-  for (int k = 0; k < 3; ++k) f[k] = d->target[k] - d->eye[k];
-  double nf = sqrt((f[0] * f[0] + f[1] * f[1]) + f[2] * f[2]);
-  if (!(nf > 0.0) || !isfinite(nf)) return OC_EINVAL;
-  for (int k = 0; k < 3; ++k) fh[k] = f[k] / nf;
-  r[0] = d->up[1] * fh[2] - d->up[2] * fh[1];
-  r[1] = d->up[2] * fh[0] - d->up[0] * fh[2];
-  r[2] = d->up[0] * fh[1] - d->up[1] * fh[0];
-  double nr = sqrt((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]);
-  if (!(nr > 0.0) || !isfinite(nr)) return OC_EINVAL;
-  for (int k = 0; k < 3; ++k) rh[k] = r[k] / nr;
-  uh[0] = fh[1] * rh[2] - fh[2] * rh[1];
-  uh[1] = fh[2] * rh[0] - fh[0] * rh[2];
-  uh[2] = fh[0] * rh[1] - fh[1] * rh[0];
-  double s, foot;
-  if (d->kind == 0) {
-    if (!(d->fov_y > 0.0) || !(d->fov_y < 3.0)) return OC_EINVAL;
-    double th = tan(0.5 * d->fov_y);
-    s = th / (double)d->H;
-    foot = 2.0 * nf * th / (double)d->H;
-  } else {
-    if (!(d->ortho_height > 0.0) || !isfinite(d->ortho_height)) return OC_EINVAL;
-    s = d->ortho_height / (2.0 * (double)d->H);
-    foot = d->ortho_height / (double)d->H;
-  }
-  out->kind = d->kind;
-  out->W = d->W;
-  out->H = d->H;
-  for (int k = 0; k < 3; ++k) {
-    out->O[k] = rne_fix(d->eye[k]);
-    out->F[k] = rne_fix(fh[k]);
-    out->U[k] = rne_fix(rh[k] * s);
-    out->V[k] = rne_fix(uh[k] * s);
-  }
-  /* bounds: origins in [-2^30, 2^30), directions in (-2^30, 2^30) */
-  const int64_t lim = (int64_t)1 << 30;
-  for (int k = 0; k < 3; ++k) {
-    int64_t span = (int64_t)(d->W - 1) * llabs(out->U[k]) + (int64_t)(d->H - 1) * llabs(out->V[k]);
-    if (out->O[k] < -lim || out->O[k] >= lim) return OC_EINVAL;
-    if (d->kind == 0) {
-      if (llabs(out->F[k]) + span >= lim) return OC_EINVAL;
-    } else {
-      if (out->O[k] - span < -lim || out->O[k] + span >= lim) return OC_EINVAL;
-      if (llabs(out->F[k]) >= lim) return OC_EINVAL;
-    }
-  }
-  int32_t L;
-  if (d->max_level >= 0) {
-    if (d->max_level > MAX_LEVEL) return OC_EINVAL;
-    L = d->max_level;
-  } else {
-    /* smallest L >= 0 whose cell side 2^-L is no larger than the pixel footprint */
-    L = 0;
-    while (L < 64 && ldexp(1.0, -L) > foot) ++L;
-    L += d->level_bias;
-    if (L < 0) L = 0;
-    if (L > MAX_LEVEL) L = MAX_LEVEL;
-    if (tree_lmax >= 0 && L > tree_lmax) L = tree_lmax;
-  }
-  out->max_level = L;
-  return OC_OK;
-}
 
 /* Integer ray of pixel (i, j): through the pixel centre, j = 0 at the bottom. */
 static void pixel_ray(const oc_camera* C, int64_t i, int64_t j, int64_t o[3], int64_t dv[3]) {
@@ -481,12 +397,14 @@ static void neum_add(neum* a, double x) {
  *                  |v_0 dh_0| + |v_1 dh_1| + |v_2 dh_2| for |f|, the size of
  *                  the terms whose single-precision dot product a renderer
  *                  rounds (the bound for a rounded dot product of n terms is
- *                  about n eps times the sum of their magnitudes).
+ *                  about n eps times the sum of their magnitudes);
+ *                  out_absdot = sum(w |f| chord) / sum(w chord), the weighted
+ *                  mean of |f| itself (equal to out_absf without los).
  * out_count = number of cells on each ray.  Any output may be NULL.
  */
 int oc_render(const oc_tree* T, const oc_camera* C, int32_t op, int32_t v_field, int32_t w_field, int32_t los,
               const int64_t* ray_ids, int64_t nrays, double* out_val, float* out_max, double* out_aux,
-              double* out_absf, int32_t* out_count, int32_t nthreads) {
+              double* out_absf, double* out_absdot, int32_t* out_count, int32_t nthreads) {
   if (!T || !C) return OC_EINVAL;
   if (op < 0 || op > 2) return OC_EINVAL;
   if (v_field < 0 || v_field + (los ? 2 : 0) >= T->nfields) return OC_EINVAL;
@@ -528,7 +446,7 @@ int oc_render(const oc_tree* T, const oc_camera* C, int32_t op, int32_t v_field,
         const float* wf = T->v32 + (int64_t)w_field * T->n;
         double dn = sqrt((double)((i128)d[0] * d[0] + (i128)d[1] * d[1] + (i128)d[2] * d[2]));
         double dh[3] = {(double)d[0] / dn, (double)d[1] / dn, (double)d[2] / dn};
-        neum num = {0, 0}, den = {0, 0}, ab = {0, 0};
+        neum num = {0, 0}, den = {0, 0}, ab = {0, 0}, ad = {0, 0};
         for (int64_t k = 0; k < B.n; ++k) {
           int64_t nd = B.s[k].node;
           double f, fa;
@@ -546,11 +464,13 @@ int oc_render(const oc_tree* T, const oc_camera* C, int32_t op, int32_t v_field,
           neum_add(&num, wl * f);
           neum_add(&den, wl);
           neum_add(&ab, wl * fa);
+          neum_add(&ad, wl * fabs(f));
         }
         double W = den.s + den.c;
         if (out_val) out_val[r] = W != 0.0 ? (num.s + num.c) / W : 0.0;
         if (out_aux) out_aux[r] = W;
         if (out_absf) out_absf[r] = W != 0.0 ? (ab.s + ab.c) / W : 0.0;
+        if (out_absdot) out_absdot[r] = W != 0.0 ? (ad.s + ad.c) / W : 0.0;
       }
     }
     free(B.s);
@@ -572,7 +492,7 @@ int oc_trace(const oc_tree* T, const oc_camera* C, const int64_t* ray_ids, int64
   if (!T || !C || !offsets || nrays < 0) return OC_EINVAL;
   int32_t* cnt = (int32_t*)malloc(sizeof(int32_t) * (nrays > 0 ? nrays : 1));
   if (!cnt) return OC_ENOMEM;
-  int rc = oc_render(T, C, OC_MAX, 0, -1, 0, ray_ids, nrays, NULL, NULL, NULL, NULL, cnt, nthreads);
+  int rc = oc_render(T, C, OC_MAX, 0, -1, 0, ray_ids, nrays, NULL, NULL, NULL, NULL, NULL, cnt, nthreads);
   if (rc) { free(cnt); return rc; }
   offsets[0] = 0;
   for (int64_t r = 0; r < nrays; ++r) offsets[r + 1] = offsets[r] + cnt[r];

@@ -309,25 +309,14 @@ amr_status amr_batch_create(const amr_tree* const* trees, int32_t ntrees, const 
     if (ti < 0 || ti >= ntrees || ci < 0 || ci >= ncams) return fail(AMR_EINVAL, "pair index out of range");
     const amr_tree* t = trees[ti];
     const amr_camera* c = &cams[ci];
-    if (!t) return fail(AMR_EINVAL, "null tree");
-    if (t->info.host_only) return fail(AMR_EINVAL, "host_only tree cannot be rendered");
+    amr_status cs = check_render_common(t, c);
+    if (cs) return cs;
     if (!outs[k] || ((uintptr_t)outs[k] & 3) || (auxs && ((uintptr_t)auxs[k] & 3)))
       return fail(AMR_EINVAL, "null or misaligned output");
-    if (c->W < 1 || c->H < 1 || c->W > 32768 || c->H > 32768 || c->max_level < 0 || c->max_level > kMaxLevel ||
-        (c->kind != 0 && c->kind != 1))
-      return fail(AMR_EINVAL, "bad camera");
     const int nf = t->info.nfields;
     if (o.field < 0 || o.field + ((op == AMR_WMEAN && o.los_velocity) ? 2 : 0) >= nf)
       return fail(AMR_EINVAL, "field index out of range");
     if (op == AMR_WMEAN && (o.weight_field < 0 || o.weight_field >= nf)) return fail(AMR_EINVAL, "bad weight field");
-    const int64_t lim = int64_t(1) << 30;
-    for (int a = 0; a < 3; ++a) {
-      const int64_t span = (int64_t)(c->W - 1) * std::llabs(c->U[a]) + (int64_t)(c->H - 1) * std::llabs(c->V[a]);
-      if (c->O[a] < -lim || c->O[a] >= lim) return fail(AMR_EINVAL, "camera origin out of range");
-      if (c->kind == 0 ? std::llabs(c->F[a]) + span >= lim
-                       : (c->O[a] - span < -lim || c->O[a] + span >= lim || std::llabs(c->F[a]) >= lim))
-        return fail(AMR_EINVAL, "camera out of range");
-    }
     BatchImage& I = imgs[k];
     I.t = t->view;
     I.c = camera_view(*c);

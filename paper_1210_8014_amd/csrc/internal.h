@@ -34,6 +34,12 @@ amr_status fail(amr_status st, const std::string& msg);
 
 CameraView camera_view(const amr_camera& c);
 
+// Checks shared by every entry point that walks rays: a renderable tree
+// and a camera record inside the integer ranges the kernels rely on (image
+// size, maximum level, kind, origin and direction bounds, non-zero
+// orthographic direction).  AMR_EINVAL with a message otherwise.
+amr_status check_render_common(const amr_tree* t, const amr_camera* cam);
+
 struct RenderArgs {
   TreeView t;
   CameraView c;

@@ -900,9 +900,10 @@ int64_t amr_lod_tiles(int32_t W, int32_t H) {
 namespace {
 amr_status launch_features(const amr_tree* t, const amr_camera* cam, int32_t coarse_level, uint16_t* feat,
                            unsigned long long* zero_stats, unsigned long long* zero_slots, amr_stream s) {
-  if (!t || !cam || !feat) return fail(AMR_EINVAL, "null argument");
-  if (t->info.host_only) return fail(AMR_EINVAL, "host_only tree");
-  if (coarse_level < 0 || coarse_level > kMaxLevel || cam->W < 1 || cam->H < 1) return fail(AMR_EINVAL, "bad level");
+  amr_status cs = check_render_common(t, cam);
+  if (cs) return cs;
+  if (!feat) return fail(AMR_EINVAL, "null argument");
+  if (coarse_level < 0 || coarse_level > kMaxLevel) return fail(AMR_EINVAL, "bad level");
   const int tx = (cam->W + kTile - 1) / kTile, ty = (cam->H + kTile - 1) / kTile;
   // log2 of the pixel footprint in units of the coarse cell side: the
   // camera record's step length over |F| (perspective, at unit distance) or
@@ -1028,8 +1029,9 @@ amr_status amr_render_lod(const amr_tree* t, const amr_camera* cam, amr_op op, c
                           const amr_render_opts* opts, float* out, float* aux, int8_t* tile_levels,
                           const int8_t* forced_levels, void* workspace, int64_t workspace_bytes, int64_t* stats,
                           amr_stream s) {
-  if (!t || !cam || !m || !out || !workspace || !stats) return fail(AMR_EINVAL, "null argument");
-  if (t->info.host_only) return fail(AMR_EINVAL, "host_only tree");
+  amr_status cs = check_render_common(t, cam);
+  if (cs) return cs;
+  if (!m || !out || !workspace || !stats) return fail(AMR_EINVAL, "null argument");
   if (op != AMR_SUM && op != AMR_MAX && op != AMR_WMEAN) return fail(AMR_EINVAL, "bad op");
   if (workspace_bytes < amr_lod_workspace_bytes(cam->W, cam->H)) return fail(AMR_ECAPACITY, "workspace too small");
   if (((uintptr_t)workspace & 255) || ((uintptr_t)stats & 7)) return fail(AMR_EINVAL, "misaligned workspace/stats");

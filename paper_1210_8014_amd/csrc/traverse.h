@@ -242,7 +242,8 @@ AMR_HD bool setup_ray(const CameraView& C, int i, int j, Ray& R, Entry& E) {
     }
     if (R.d[k] == 0 && (R.o[k] < 0 || R.o[k] >= kOne)) miss = true;
   }
-  if (miss) return false;
+  // a zero direction spends no positive length anywhere
+  if (miss || (R.d[0] | R.d[1] | R.d[2]) == 0) return false;
   // entry parameter: max(0, max over axes of -o_k / d_k), kept as en / ed
   int a = -1;
   int32_t en = 0, ed = 1, oa = 0;

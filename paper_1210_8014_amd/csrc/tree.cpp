@@ -134,6 +134,29 @@ inline int ctz128(u128 k) {
 
 using namespace amr;
 
+amr_status amr::check_render_common(const amr_tree* t, const amr_camera* cam) {
+  if (!t || !cam) return fail(AMR_EINVAL, "null tree or camera");
+  if (t->info.host_only) return fail(AMR_EINVAL, "host_only tree cannot be rendered");
+  if (cam->W < 1 || cam->H < 1 || cam->W > 32768 || cam->H > 32768) return fail(AMR_EINVAL, "bad image size");
+  if (cam->max_level < 0 || cam->max_level > kMaxLevel) return fail(AMR_EINVAL, "bad max_level");
+  if (cam->kind != 0 && cam->kind != 1) return fail(AMR_EINVAL, "bad camera kind");
+  // re-check the integer ranges the kernels rely on (records may be hand-made)
+  const int64_t lim = int64_t(1) << 30;
+  for (int k = 0; k < 3; ++k) {
+    const int64_t span = (int64_t)(cam->W - 1) * std::llabs(cam->U[k]) + (int64_t)(cam->H - 1) * std::llabs(cam->V[k]);
+    if (cam->O[k] < -lim || cam->O[k] >= lim) return fail(AMR_EINVAL, "camera origin out of range");
+    if (cam->kind == 0) {
+      if (std::llabs(cam->F[k]) + span >= lim) return fail(AMR_EINVAL, "camera direction out of range");
+    } else {
+      if (cam->O[k] - span < -lim || cam->O[k] + span >= lim) return fail(AMR_EINVAL, "camera origin out of range");
+      if (std::llabs(cam->F[k]) >= lim) return fail(AMR_EINVAL, "camera direction out of range");
+    }
+  }
+  if (cam->kind == 1 && cam->F[0] == 0 && cam->F[1] == 0 && cam->F[2] == 0)
+    return fail(AMR_EINVAL, "zero direction");
+  return AMR_OK;
+}
+
 extern "C" {
 
 const char* amr_last_error(void) { return g_err.c_str(); }
@@ -509,29 +532,6 @@ amr_status amr_set_camera(const amr_camera_desc* d, const amr_tree* t, amr_camer
   }
   c.max_level = lv;
   *out = c;
-  return AMR_OK;
-}
-
-static amr_status check_render_common(const amr_tree* t, const amr_camera* cam) {
-  if (!t || !cam) return fail(AMR_EINVAL, "null tree or camera");
-  if (t->info.host_only) return fail(AMR_EINVAL, "host_only tree cannot be rendered");
-  if (cam->W < 1 || cam->H < 1 || cam->W > 32768 || cam->H > 32768) return fail(AMR_EINVAL, "bad image size");
-  if (cam->max_level < 0 || cam->max_level > kMaxLevel) return fail(AMR_EINVAL, "bad max_level");
-  if (cam->kind != 0 && cam->kind != 1) return fail(AMR_EINVAL, "bad camera kind");
-  // re-check the integer ranges the kernels rely on (records may be hand-made)
-  const int64_t lim = int64_t(1) << 30;
-  for (int k = 0; k < 3; ++k) {
-    const int64_t span = (int64_t)(cam->W - 1) * std::llabs(cam->U[k]) + (int64_t)(cam->H - 1) * std::llabs(cam->V[k]);
-    if (cam->O[k] < -lim || cam->O[k] >= lim) return fail(AMR_EINVAL, "camera origin out of range");
-    if (cam->kind == 0) {
-      if (std::llabs(cam->F[k]) + span >= lim) return fail(AMR_EINVAL, "camera direction out of range");
-    } else {
-      if (cam->O[k] - span < -lim || cam->O[k] + span >= lim) return fail(AMR_EINVAL, "camera origin out of range");
-      if (std::llabs(cam->F[k]) >= lim) return fail(AMR_EINVAL, "camera direction out of range");
-    }
-  }
-  if (cam->kind == 1 && cam->F[0] == 0 && cam->F[1] == 0 && cam->F[2] == 0)
-    return fail(AMR_EINVAL, "zero direction");
   return AMR_OK;
 }
 

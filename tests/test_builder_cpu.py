@@ -147,18 +147,20 @@ def test_camera_records_match_oracle(oracle_lib):
             ref = oracle_lib.set_camera(d, 16)
         except ValueError:
             with pytest.raises(amr.AmrError):
-                amr.set_camera(d, None) if False else _set_with_lmax(d, 16)
+                _set_with_lmax(d, 16)
             continue
         got = _set_with_lmax(d, 16)
         assert got.as_dict() == ref.as_dict(), d
         n_ok += 1
     assert n_ok > 1000
-    for name in ("tiny_camera.json", "two_level.json"):
+    for name in ("tiny_camera.json", "two_level.json", "persp_axis.json", "persp_oblique.json"):
         import json
         g = json.load(open(os.path.join(ROOT, "tests", "golden", name)))
         c = amr.set_camera(g["camera"])
         for k in ("O", "F", "U", "V"):
-            assert list(getattr(c, k)) == g["record"][k]
+            assert list(getattr(c, k)) == g["record"][k], (name, k)
+        if "auto_level" in g:
+            assert c.max_level == g["auto_level"], name
 
 
 _lmax_trees = {}

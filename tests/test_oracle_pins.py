@@ -120,6 +120,53 @@ def test_golden_tiny_camera(oracle_lib):
         assert d.tolist() == [0, 0, 1 << 28]
 
 
+@pytest.mark.parametrize("name", ["persp_axis.json", "persp_oblique.json"])
+def test_golden_perspective_records(oracle_lib, name):
+    """Hand-derived perspective records: pins the half-pixel step
+    tan(fov_y/2)/H (vertical field of view), the image axes and the
+    automatic level."""
+    g = _golden(name)
+    cam = oracle_lib.set_camera(g["camera"])
+    for k in ("O", "F", "U", "V"):
+        assert list(getattr(cam, k)) == g["record"][k], k
+    assert cam.max_level == g["auto_level"]
+    # pixel (0, 0) looks through the lower-left pixel centre: a = 1 - W, b = 1 - H
+    o, d = oracle_lib.pixel_ray(cam, 0, 0)
+    W, H = g["camera"]["W"], g["camera"]["H"]
+    F, U, V = (np.array(g["record"][k]) for k in ("F", "U", "V"))
+    assert o.tolist() == g["record"]["O"]
+    assert d.tolist() == (F + (1 - W) * U + (1 - H) * V).tolist()
+
+
+def test_field_of_view_edge_ray(oracle_lib):
+    """The top edge of the image (b = H) lies fov_y/2 off the view axis and
+    the right edge (a = W) atan(W/H tan(fov_y/2)) off it, to within the
+    rounding of the integer record: |H |V| / |F| - tan(fov_y/2)| is at most
+    (H + 1) sqrt(3)/2 / (|F| - 1)."""
+    rng = np.random.default_rng(7)
+    n = 0
+    for _ in range(400):
+        eye = rng.uniform(-1.0, 2.0, 3)
+        tgt = rng.uniform(0.2, 0.8, 3)
+        W, H = (int(v) for v in rng.integers(1, 4000, 2))
+        fov = rng.uniform(0.05, 1.5)
+        d = amrgen.camera("persp", eye, tgt, rng.normal(size=3), W, H, fov_y=fov)
+        try:
+            c = oracle_lib.set_camera(d)
+        except ValueError:
+            continue
+        F, U, V = (np.array(list(getattr(c, k)), np.float64) for k in ("F", "U", "V"))
+        nF = np.linalg.norm(F)
+        bound = (H + 1) * math.sqrt(3) / 2 / (nF - 1)
+        assert abs(H * np.linalg.norm(V) / nF - math.tan(fov / 2)) <= bound + 1e-15
+        assert abs(H * np.linalg.norm(U) / nF - math.tan(fov / 2)) <= bound + 1e-15
+        # the three axes are orthogonal to within the rounding
+        assert abs(F @ U) <= 0.87 * (np.abs(F).sum() + np.abs(U).sum())
+        assert abs(F @ V) <= 0.87 * (np.abs(F).sum() + np.abs(V).sum())
+        n += 1
+    assert n > 300
+
+
 def test_camera_rejects(oracle_lib):
     base = amrgen.camera("persp", (0.5, 0.5, 2.0), (0.5, 0.5, 0.5), (0, 1, 0), 64, 64, fov_y=0.5)
     oracle_lib.set_camera(base)
@@ -408,3 +455,59 @@ def test_tree_rejects_bad_leaf_sets(oracle_lib):
         oracle_lib.Tree(mk([0], [0], [0], [0], np.array([[np.nan]], np.float32)))
     T = oracle_lib.Tree(L.permuted(3))
     assert T.nodes == 9
+
+
+# ------------------------------------------------- hand-worked sums
+
+def _leaves_level(level, fields_of):
+    """Uniform level-`level` tree; fields_of(ix, iy, iz) -> list of fields."""
+    n = 1 << level
+    ix, iy, iz = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    ix, iy, iz = ix.ravel(), iy.ravel(), iz.ravel()
+    vals = np.array([fields_of(int(a), int(b), int(c)) for a, b, c in zip(ix, iy, iz)], np.float32).T
+    return amrgen.Leaves(np.full(ix.size, level, np.int32), ix.astype(np.int32), iy.astype(np.int32),
+                         iz.astype(np.int32), np.ascontiguousarray(vals), vals.shape[0])
+
+
+def test_golden_wmean_three_cells(oracle_lib):
+    """Hand-worked sum, maximum, line-of-sight weighted mean and both of its
+    error scales on three cells (pins the projection, the weights and the
+    absf / absdot scales term by term)."""
+    g = _golden("wmean_three_cells.json")
+    cells = {tuple(int(v) for v in k.split(",")): v for k, v in g["cells"].items()}
+    L = _leaves_level(1, lambda a, b, c: cells.get((a, b, c), g["other"]))
+    T = oracle_lib.Tree(L)
+    cam = T.camera(g["camera"])
+    e = g["expect"]
+    r2 = math.sqrt(2.0)
+    s = T.render(cam, oracle_lib.SUM)
+    assert s["count"][0] == e["count"]
+    assert s["val"][0] == pytest.approx(e["sum_over_sqrt2"] * r2, rel=1e-15)
+    assert T.render(cam, oracle_lib.MAX)["max"][0] == e["max"]
+    w = T.render(cam, oracle_lib.WMEAN, field=1, weight=0, los=True)
+    assert w["val"][0] == pytest.approx(e["wmean_over_sqrt2"] * r2, rel=1e-14)
+    assert w["aux"][0] == pytest.approx(e["weight_over_sqrt2"] * r2, rel=1e-15)
+    assert w["absf"][0] == pytest.approx(e["absf_over_sqrt2"] * r2, rel=1e-14)
+    assert w["absdot"][0] == pytest.approx(e["absdot_over_sqrt2"] * r2, rel=1e-14)
+    sc = T.render(cam, oracle_lib.WMEAN, field=1, weight=0, los=False)
+    assert abs(sc["val"][0]) <= 1e-15
+    assert sc["absf"][0] == pytest.approx(e["scalar_vx"]["absf"], rel=1e-15)
+    assert sc["absdot"][0] == pytest.approx(e["scalar_vx"]["absf"], rel=1e-15)
+
+
+def test_golden_cancelling_sum_needs_compensation(oracle_lib):
+    """A sum whose exact value plain fp64 accumulation loses: the oracle's
+    compensated sum returns it exactly (pins the compensation)."""
+    g = _golden("cancelling_sum.json")
+    pat = g["pattern"]
+    L = _leaves_level(g["level"], lambda a, b, c: [pat[a % 4]])
+    T = oracle_lib.Tree(L)
+    cam = T.camera(g["camera"])
+    r = T.render(cam, oracle_lib.SUM)
+    assert r["count"][0] == 1 << g["level"]
+    assert r["val"][0] == g["expect"]["sum"]
+    # the fixture's premise: plain left-to-right fp64 gets it wrong
+    acc = 0.0
+    for k in range(1 << g["level"]):
+        acc += float(np.float32(pat[k % 4])) * 2.0 ** -g["level"]
+    assert acc == g["expect"]["plain_left_to_right"]
