@@ -359,9 +359,21 @@ amr_status amr_render_lod(const amr_tree* t, const amr_camera* cam, amr_op op, c
 /* ---------------------------------------------------------------- debug */
 
 /* Segments (cells met) per ray for every pixel: counts (device int32 H x W,
- * may be NULL) and their total (device int64, 1 element, overwritten). */
+ * may be NULL) and their total (device int64, 1 element, overwritten).
+ * The counts come from the walk the renders time (the unsplit whole-ray
+ * walk), so they are the segment counts of the benchmarked launches. */
 amr_status amr_count_segments(const amr_tree* t, const amr_camera* cam, int32_t* counts, int64_t* total,
                               amr_stream s);
+
+/* Distinct cells met by the rays of an image (the compulsory traffic of a
+ * render is that count times the bytes read per cell).  bitmap: device
+ * uint32, ceil(ncells / 32) words, bit c for cell c (the cell index of the
+ * tree's layout); cells met get their bit set (bits already set stay set,
+ * so several images accumulate, and the caller clears the bitmap to
+ * start).  distinct: device int64, increased by the number of bits this
+ * call set.  Calls that overlap on one bitmap count each cell once. */
+amr_status amr_mark_cells(const amr_tree* t, const amr_camera* cam, uint32_t* bitmap, int64_t* distinct,
+                          amr_stream s);
 
 /* Cell sequences of the rays ray_ids[0..n) (pixel index j*W + i, device
  * int64).  offsets (device int64, n + 1) must already hold the exclusive

@@ -10,7 +10,9 @@ Plain NumPy, fp64 unless stated:
     probability of too-shallow levels)
     and its analytic gradient, pinned by central finite differences;
   * per-tile labels from renders at every level, and the plan (quantile
-    level, confidence fallback).
+    level, confidence fallback);
+  * the Adam update (Kingma and Ba: moment estimates with bias correction),
+    pinned by its closed forms for constant and alternating gradients.
 Parameter layout: W1[32][64], b1[64], W2[64][64], b2, W3[64][64], b3,
 W4[64][16], b4[16].
 """
@@ -196,3 +198,15 @@ def plan(logits, q, conf_thresh, full_level):
     fb = (p.max(axis=1) < conf_thresh) | (conf_thresh >= 1.0)
     lev = np.where(fb, full_level, lev)
     return np.minimum(lev, full_level), fb
+
+
+def adam(params, grads, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step, step number t >= 1: returns (params, m, v) after it.
+    m <- beta1 m + (1 - beta1) g;  v <- beta2 v + (1 - beta2) g^2;
+    params <- params - lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps)."""
+    g = np.asarray(grads, np.float64)
+    m = beta1 * np.asarray(m, np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, np.float64) + (1.0 - beta2) * g * g
+    mh = m / (1.0 - beta1 ** t)
+    vh = v / (1.0 - beta2 ** t)
+    return np.asarray(params, np.float64) - lr * mh / (np.sqrt(vh) + eps), m, v

@@ -179,6 +179,13 @@ def count_segments(tree: Tree, cam: Camera, total, counts=None, stream=None):
     _check(lib().amr_count_segments(tree.handle, ctypes.byref(cam), _ptr(counts), _ptr(total), _stream(stream)))
 
 
+def mark_cells(tree: Tree, cam: Camera, bitmap, distinct, stream=None):
+    """Sets bit c of ``bitmap`` (device int32/uint32, ceil(ncells/32) words)
+    for every cell c the image's rays meet and adds the number of newly set
+    bits to ``distinct`` (device int64 of one element)."""
+    _check(lib().amr_mark_cells(tree.handle, ctypes.byref(cam), _ptr(bitmap), _ptr(distinct), _stream(stream)))
+
+
 def count_rays(tree: Tree, cam: Camera, ray_ids, counts, stream=None):
     _check(lib().amr_count_rays(tree.handle, ctypes.byref(cam), _ptr(ray_ids), int(ray_ids.numel()), _ptr(counts),
                                 _stream(stream)))

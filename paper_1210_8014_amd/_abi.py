@@ -62,6 +62,7 @@ SIGNATURES = {
     "amr_count_segments": (_i32, [_vp, ctypes.POINTER(Camera), _vp, _vp, _vp]),
     "amr_trace_rays": (_i32, [_vp, ctypes.POINTER(Camera), _vp, _i64, _vp, _vp, _vp]),
     "amr_count_rays": (_i32, [_vp, ctypes.POINTER(Camera), _vp, _i64, _vp, _vp]),
+    "amr_mark_cells": (_i32, [_vp, ctypes.POINTER(Camera), _vp, _vp, _vp]),
     "amr_batch_create": (_i32, [ctypes.POINTER(_vp), _i32, ctypes.POINTER(Camera), _i32, ctypes.POINTER(_i32), _i32,
                                 _i32, ctypes.POINTER(RenderOpts), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                 ctypes.POINTER(_vp)]),

@@ -63,6 +63,7 @@ AMR_HD int center_out(int b, int px, int py) {
 // Kernel launchers (render.hip).  Return a hipError_t as int.
 int launch_render(int op, int variant, const RenderArgs& a, void* stream);
 int launch_count_all(const TreeView& t, const CameraView& c, int32_t* counts, int64_t* total, void* stream);
+int launch_mark(const TreeView& t, const CameraView& c, uint32_t* bits, int64_t* fresh, void* stream);
 int launch_rays(const TreeView& t, const CameraView& c, const int64_t* ray_ids, int64_t n, const int64_t* offsets,
                 int32_t* cells, int32_t* counts, void* stream);
 int variant_count();

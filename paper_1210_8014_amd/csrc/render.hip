@@ -125,7 +125,7 @@ __global__ __launch_bounds__(256) void k_count_all(TreeView T, CameraView C, int
     Entry E;
     if (setup_ray(C, i, j, R, E)) {
       CountVis v;
-      n = walk_ray(T, R, E, C.max_level, v);
+      n = walk_fast<CountVis, true>(T, R, E, C.max_level, v);  // the benchmarked walk
     }
     if (counts) counts[pix] = n;
   }
@@ -133,6 +133,23 @@ __global__ __launch_bounds__(256) void k_count_all(TreeView T, CameraView C, int
   unsigned long long s = (unsigned long long)n;
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   if ((threadIdx.x & 63) == 0 && s) atomicAdd(total, s);
+}
+
+__global__ __launch_bounds__(256) void k_mark(TreeView T, CameraView C, uint32_t* bits, unsigned long long* fresh) {
+  const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long f = 0;
+  if (pix < (int64_t)C.W * C.H) {
+    Ray R;
+    Entry E;
+    if (setup_ray(C, (int)(pix % C.W), (int)(pix / C.W), R, E)) {
+      MarkVis v;
+      v.bits = bits;
+      walk_fast<MarkVis, true>(T, R, E, C.max_level, v);
+      f = v.fresh;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) f += __shfl_down(f, off, 64);
+  if ((threadIdx.x & 63) == 0 && f) atomicAdd(fresh, f);
 }
 
 __global__ __launch_bounds__(256) void k_rays(TreeView T, CameraView C, const int64_t* ray_ids, int64_t n,
@@ -242,6 +259,14 @@ int launch_count_all(const TreeView& t, const CameraView& c, int32_t* counts, in
   const int64_t n = (int64_t)c.W * c.H;
   hipLaunchKernelGGL(k_count_all, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, t, c, counts,
                      (unsigned long long*)total);
+  return (int)hipGetLastError();
+}
+
+int launch_mark(const TreeView& t, const CameraView& c, uint32_t* bits, int64_t* fresh, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = (int64_t)c.W * c.H;
+  hipLaunchKernelGGL(k_mark, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, t, c, bits,
+                     (unsigned long long*)fresh);
   return (int)hipGetLastError();
 }
 

@@ -783,6 +783,27 @@ struct TraceVis {
   }
 };
 
+// Sets bit `node` of a bitmap for every cell met and counts the bits it
+// was first to set (distinct cells over all rays of a launch).
+struct MarkVis {
+  static constexpr bool kNeedsLength = false;
+  uint32_t* bits;
+  unsigned long long fresh = 0;
+  AMR_HD void fetch(int32_t) {}
+  AMR_HD void fetch0(int32_t, float) {}
+  AMR_HD void seg(int32_t node, int, float, int32_t, int32_t, int32_t) {
+    const uint32_t w = (uint32_t)node >> 5, b = 1u << ((uint32_t)node & 31u);
+    if (bits[w] & b) return;  // already marked (plain read: most repeats end here)
+#if defined(__HIP_DEVICE_COMPILE__)
+    const uint32_t old = atomicOr(bits + w, b);
+#else
+    const uint32_t old = bits[w];
+    bits[w] = old | b;
+#endif
+    if (!(old & b)) ++fresh;
+  }
+};
+
 // ------------------------------------------------------------ one pixel
 
 enum { kOpSum = 0, kOpMax = 1, kOpWMean = 2 };
@@ -850,6 +871,8 @@ AMR_HD void render_pixel(const TreeView& T, const CameraView& C, int field, int 
 
 // Number of cells on the ray of pixel (i, j); with cells != NULL they are
 // also written (4 int32 each), but only if exactly `cap` of them exist.
+// Both passes take walk_fast over the whole ray, the walk the batched and
+// single-image renders time, so the sequences and counts are that walk's.
 AMR_HD int32_t trace_pixel(const TreeView& T, const CameraView& C, int max_level, int i, int j, int32_t* cells,
                            int64_t cap) {
   Ray R;
@@ -857,14 +880,14 @@ AMR_HD int32_t trace_pixel(const TreeView& T, const CameraView& C, int max_level
   if (!setup_ray(C, i, j, R, E)) return 0;
   const Entry E0 = E;
   CountVis c;
-  const int32_t m = walk_ray(T, R, E, max_level, c);
+  const int32_t m = walk_fast<CountVis, true>(T, R, E, max_level, c);
   if (!cells || m != cap) return m;
   TraceVis v;
   v.out = cells;
   AMR_UNROLL
   for (int k = 0; k < 3; ++k) v.flip_bits[k] = R.flip[k] ? 1 : 0;
   E = E0;
-  walk_ray(T, R, E, max_level, v);
+  walk_fast<TraceVis, true>(T, R, E, max_level, v);
   return m;
 }
 

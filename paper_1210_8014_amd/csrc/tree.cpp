@@ -581,6 +581,17 @@ amr_status amr_count_segments(const amr_tree* t, const amr_camera* cam, int32_t*
   return AMR_OK;
 }
 
+amr_status amr_mark_cells(const amr_tree* t, const amr_camera* cam, uint32_t* bitmap, int64_t* distinct,
+                          amr_stream s) {
+  amr_status st = check_render_common(t, cam);
+  if (st) return st;
+  if (!bitmap || !distinct) return fail(AMR_EINVAL, "null argument");
+  if (((uintptr_t)bitmap & 3) || ((uintptr_t)distinct & 7)) return fail(AMR_EINVAL, "misaligned output");
+  int e = launch_mark(t->view, camera_view(*cam), bitmap, distinct, s);
+  if (e) return fail(AMR_EHIP, std::string("mark launch failed: ") + dev_error_string(e));
+  return AMR_OK;
+}
+
 amr_status amr_trace_rays(const amr_tree* t, const amr_camera* cam, const int64_t* ray_ids, int64_t n,
                           const int64_t* offsets, int32_t* cells, amr_stream s) {
   amr_status st = check_render_common(t, cam);

@@ -125,3 +125,50 @@ def test_tuners_choose_valid_configurations(tmp_path):
     torch.cuda.synchronize()
     assert torch.equal(a.view(torch.int32), b.view(torch.int32))
     assert amr.apply_tuning(t, cam, amr.SUM, cache=cache) == v
+
+
+def test_batched_disk_snapshots_match_oracle_on_sampled_rays():
+    """A slice of the batched workload at its real shape: two disk snapshots
+    (seeds 0 and 1: 5.3M and 8.2M leaves, density and velocity) under all
+    64 orbit cameras (sides 512..2048, multiples of 16) = 128 images in one
+    graph launch of the benchmarked grid configuration, sum and the
+    line-of-sight weighted mean; every 8th image is checked against the
+    oracle on a seeded 1% ray sample."""
+    import oracle
+    import paper_1210_8014_amd as amr
+    from tests import parity
+
+    leaves = [amrgen.scene("batch", seed=s) for s in (0, 1)]
+    trees = [amr.Tree(L) for L in leaves]
+    descs = amrgen.orbit_cameras(64, seed=0)
+    cams = [amr.set_camera(d) for d in descs]
+    pairs = [(t, c) for t in range(2) for c in range(64)]
+    checked = list(range(0, len(pairs), 8))
+    OTs = [oracle.Tree(L) for L in leaves]
+    rng = np.random.default_rng(42)
+    samples = {k: np.sort(rng.choice(cams[pairs[k][1]].W * cams[pairs[k][1]].H,
+                                     cams[pairs[k][1]].W * cams[pairs[k][1]].H // 100, replace=False))
+               for k in checked}
+    for op in ("sum", "wmean"):
+        o = amr.SUM if op == "sum" else amr.WMEAN
+        kw = dict(field=1, weight=0, los=True) if op == "wmean" else {}
+        outs = [torch.empty(cams[c].W * cams[c].H, device="cuda") for _, c in pairs]
+        auxs = [torch.empty_like(x) for x in outs] if op == "wmean" else None
+        B = amr.Batch(trees, cams, pairs, o, outs, auxs, **kw)
+        B.set_config(amr.batch_configs().index("p8x8_fast_grid"))
+        B.run()
+        torch.cuda.synchronize()
+        worst = 0.0
+        for k in checked:
+            t, c = pairs[k]
+            ocam = OTs[t].camera(descs[c])
+            assert ocam.as_dict() == cams[c].as_dict()
+            r = samples[k]
+            got = outs[k].cpu().numpy()[r]
+            if op == "sum":
+                worst = max(worst, parity.check_sum(got, OTs[t].render(ocam, oracle.SUM, rays=r)["val"], f"image {k}"))
+            else:
+                ref = OTs[t].render(ocam, oracle.WMEAN, field=1, weight=0, los=True, rays=r)
+                worst = max(worst, parity.check_wmean(got, auxs[k].cpu().numpy()[r], ref, f"image {k}"))
+        log(op, "batch of", len(pairs), "images:", len(checked), "checked on 1% samples, worst", f"{worst:.2e}")
+        B.close()

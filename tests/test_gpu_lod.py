@@ -41,14 +41,58 @@ def test_mlp_forward_matches_oracle():
     torch.cuda.synchronize()
     ref, _ = OL.forward(p.astype(np.float64), X)
     got = logits.cpu().numpy().astype(np.float64)
-    scale = np.abs(ref).max()
+    bound, _ = _error_bounds(p, X, np.zeros((n, 16)), 0.0, n)
     err = np.abs(got - ref)
-    log("forward max abs err", err.max(), "scale", scale)
-    assert err.max() <= 2e-2 * scale
-    assert err.mean() <= 2e-3 * scale
+    log("forward: max |err| / bound", float((err / np.maximum(bound, 1e-30)).max()), "max |err|", err.max())
+    assert np.all(err <= bound)
+
+
+def _error_bounds(params, X, dl, e_dl, n):
+    """The oracle's forward and backward (bf16 roundings as on the device)
+    carrying, per element, a bound on |device - oracle|: a bf16 rounding
+    that falls the other way moves a value by one bf16 unit (2^-7
+    relative); an fp32 sum of up to 64 products errs by at most 2^-17 of the
+    sum of their magnitudes, a sum over n samples by n 2^-24 of it; a ReLU
+    whose input lies within its own error of zero may switch on either side,
+    which then costs the whole back-propagated value.  Returns
+    (logit bounds, {parameter name: gradient bounds})."""
+    import oracle.lod as OL
+
+    P = OL.unpack(np.asarray(params, np.float64))
+    U, A, Ag = 2.0 ** -7, 2.0 ** -17, n * 2.0 ** -24
+    hs, ehs, zs, ezs = [X], [np.zeros_like(X)], [], []
+    for L in (1, 2, 3):
+        Wa = np.abs(OL.bf16(P[f"W{L}"]))
+        z = hs[-1] @ OL.bf16(P[f"W{L}"]) + P[f"b{L}"]
+        ez = ehs[-1] @ Wa + A * (np.abs(hs[-1]) @ Wa)
+        zs.append(z)
+        ezs.append(ez)
+        hs.append(OL.bf16(np.maximum(z, 0.0)))
+        ehs.append(ez + U * np.abs(z))
+    W4a = np.abs(OL.bf16(P["W4"]))
+    e_logits = ehs[3] @ W4a + A * (np.abs(hs[3]) @ W4a)
+    dz = OL.bf16(dl)
+    edz = e_dl + U * np.abs(dl)
+    eg = {"W4": np.abs(hs[3]).T @ edz + ehs[3].T @ (np.abs(dz) + edz) + Ag * (np.abs(hs[3]).T @ np.abs(dz)),
+          "b4": edz.sum(axis=0) + Ag * np.abs(dz).sum(axis=0)}
+    for L in (3, 2, 1):
+        W = OL.bf16(P[f"W{L + 1}"])
+        da = dz @ W.T
+        eda = edz @ np.abs(W).T + A * (np.abs(dz) @ np.abs(W).T)
+        on = hs[L] > 0
+        unsure = np.abs(zs[L - 1]) <= ezs[L - 1]
+        dz = OL.bf16(da * on)
+        edz = np.where(unsure, np.abs(da) + eda, on * (eda + U * (np.abs(da) + eda)))
+        xin, exin = hs[L - 1], ehs[L - 1]
+        eg[f"W{L}"] = (np.abs(xin).T @ edz + exin.T @ (np.abs(dz) + edz) + Ag * (np.abs(xin).T @ np.abs(dz)))
+        eg[f"b{L}"] = edz.sum(axis=0) + Ag * np.abs(dz).sum(axis=0)
+    return e_logits, eg
 
 
 def test_gradients_match_oracle():
+    """Element-wise: the loss gradient w.r.t. the logits and every parameter
+    gradient against the oracle's backward (same bf16 roundings), each
+    within its propagated rounding bound (_error_bounds)."""
     import oracle.lod as OL
     from paper_1210_8014_amd import lod
 
@@ -75,16 +119,127 @@ def test_gradients_match_oracle():
     g = m.grads().astype(np.float64)
     ref_logits, ref_acts = OL.forward(p.astype(np.float64), X)
     ref_loss, ref_dl = OL.loss_and_grad(ref_logits, y, lam)
-    ref_g = OL.backward(p.astype(np.float64), X, ref_acts, ref_dl / n)
-    assert float(lsum.item()) / n == pytest.approx(ref_loss.mean(), rel=1e-2)
+    ref_dl = ref_dl / n
+    ref_g = OL.backward(p.astype(np.float64), X, ref_acts, ref_dl)
+    # loss and its logit gradient: the device's softmax is fp32 on logits
+    # that carry their own bound; allow 1e-5 of each row's largest entry
+    e_logits, _ = _error_bounds(p, X, ref_dl, 0.0, n)
+    assert float(lsum.item()) / n == pytest.approx(ref_loss.mean(), rel=1e-4)
+    dl = dlog.cpu().numpy().astype(np.float64)
+    # (softmax moves each probability by at most 2 p max|dz| under a logit
+    # change dz; with the too-shallow penalty, lambda = 2, each entry of
+    # n dloss/dlogit moves by at most 10 max|dz|)
+    e_dl = 1e-5 * np.abs(ref_dl).max(axis=1, keepdims=True) + 10.0 * e_logits.max(axis=1, keepdims=True) / n
+    assert np.all(np.abs(dl - ref_dl) <= e_dl)
+    _, eg = _error_bounds(p, X, ref_dl, e_dl, n)
     k = 0
     for name, shp in OL.SHAPES:
         sz = int(np.prod(shp))
-        a, b = g[k:k + sz], ref_g[k:k + sz]
-        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
-        log(name, "grad rel err", rel)
-        assert rel <= 3e-2, name
+        a, b, bd = g[k:k + sz], ref_g[k:k + sz], eg[name].ravel()
+        err = np.abs(a - b)
+        log(name, "grad: max |err| / bound", f"{float((err / np.maximum(bd, 1e-30)).max()):.2e}",
+            "max |err| / max |g|", f"{err.max() / np.abs(b).max():.2e}")
+        assert np.all(err <= bd), name
         k += sz
+
+
+def _dyadic_case(seed, n):
+    """Parameters, inputs and logit gradients on coarse dyadic grids (weights
+    +-1/8 at density 1/4, biases multiples of 1/8, inputs and logit gradients
+    multiples of 1/4 in [-1, 1]): every product is exact in fp32, and the
+    test checks that every sum of a matrix product stays below 2^24 units of
+    its finest bit, so fp32 sums in any order are exact too.  The network's
+    forward, backward and gradients are then exact on both sides, bf16
+    roundings included (they round the same exact values)."""
+    import oracle.lod as OL
+
+    rng = np.random.default_rng(seed)
+    p = {}
+    for name, shp in OL.SHAPES:
+        if name.startswith("W"):
+            p[name] = rng.choice([-0.125, 0.125], size=shp) * (rng.random(shp) < 0.25)
+        else:
+            p[name] = rng.integers(-2, 3, size=shp) * 0.125
+    X = rng.integers(-4, 5, size=(n, 32)) * 0.25
+    dl = rng.integers(-4, 5, size=(n, 16)) * 0.25
+    return OL.pack(p), X, dl
+
+
+def _assert_exact_fp32_products(A, B):
+    def bits(a):
+        q = 0
+        while not np.all(a * 2.0 ** q == np.round(a * 2.0 ** q)):
+            q += 1
+        return q
+
+    assert (np.abs(A) @ np.abs(B)).max() * 2.0 ** (bits(A) + bits(B)) < 2.0 ** 24
+
+
+def test_dyadic_network_is_exact_and_adam_matches():
+    """Bit-exact logits, activations and parameter gradients against the
+    oracle on dyadic data (no rounding can differ), then three Adam steps
+    (fp32 master weights on the device, fp64 in the oracle) element-wise."""
+    import oracle.lod as OL
+    from paper_1210_8014_amd import lod
+
+    n = 40  # two full 16-row blocks and a ragged one; wgrad sums 32 + 8 samples
+    P, X, dl = _dyadic_case(11, n)
+    p = OL.unpack(P)
+    ref_logits, ref_acts = OL.forward(P, X)
+    # the exactness premise, checked on the oracle's values
+    for A, B in ((X, p["W1"]), (ref_acts[0], p["W2"]), (ref_acts[1], p["W3"]), (ref_acts[2], p["W4"])):
+        _assert_exact_fp32_products(A, B)
+    dzs = OL.bf16(dl)
+    _assert_exact_fp32_products(ref_acts[2].T, dzs)
+    for L in (3, 2, 1):
+        _assert_exact_fp32_products(dzs, p[f"W{L + 1}"].T)
+        dzs = OL.bf16((dzs @ p[f"W{L + 1}"].T) * (ref_acts[L - 1] > 0))
+        _assert_exact_fp32_products((X if L == 1 else ref_acts[L - 2]).T, dzs)
+    ref_g = OL.backward(P, X, ref_acts, dl)
+
+    m = lod.LodModel(seed=0)
+    m.set_params(P.astype(np.float32))
+    xb = torch.as_tensor(OL.bf16_bits(X).view(np.int16), device="cuda")
+    logits = torch.empty((n, 16), device="cuda")
+    acts = torch.empty((3, n, 64), dtype=torch.int16, device="cuda")
+    dz = torch.empty(3 * n * 64 + n * 16, dtype=torch.int16, device="cuda")
+    dlog = torch.as_tensor(dl.astype(np.float32), device="cuda")
+    m.zero_grads()
+    m.forward(xb, n, logits, acts)
+    m.backward(xb, acts, dlog, n, dz)
+    torch.cuda.synchronize()
+    assert np.array_equal(logits.cpu().numpy().astype(np.float64), ref_logits)
+    got_acts = OL.from_bits(acts.cpu().numpy().view(np.uint16))
+    for L in range(3):
+        assert np.array_equal(got_acts[L], ref_acts[L]), L
+    g = m.grads().astype(np.float64)
+    assert np.array_equal(g, ref_g), np.flatnonzero(g != ref_g)[:8]
+    log("dyadic: logits, activations and", g.size, "gradients bit-exact;", int((g != 0).sum()), "non-zero")
+
+    # Adam: three steps with this gradient on both sides (the device's is
+    # re-accumulated at the original weights, where it is exact, before each
+    # step is taken from the updated weights)
+    lr = 1e-3
+    Pr, Mr, Vr = P.copy(), np.zeros_like(P), np.zeros_like(P)
+    cur = P.astype(np.float32)
+    for t in range(1, 4):
+        m.set_params(P.astype(np.float32))
+        m.zero_grads()
+        m.forward(xb, n, logits, acts)
+        m.backward(xb, acts, dlog, n, dz)
+        torch.cuda.synchronize()
+        assert np.array_equal(m.grads().astype(np.float64), ref_g)
+        m.set_params(cur)
+        m.adam_step(lr)
+        torch.cuda.synchronize()
+        Pr, Mr, Vr = OL.adam(Pr, ref_g, Mr, Vr, t, lr)
+        cur = m.params()
+        err = np.abs(cur.astype(np.float64) - Pr)
+        log(f"adam step {t}: max |p - p_ref| = {err.max():.2e} (lr {lr})")
+        # fp32 master weights: half an ulp of |p| per step for the stored
+        # weight, and 1e-6 relative of the step (at most lr) for its fp32
+        # arithmetic
+        assert np.all(err <= t * (2.0 ** -24 * np.abs(Pr) + 1e-6 * lr)), t
 
 
 def test_features_match_oracle():
@@ -96,9 +251,10 @@ def test_features_match_oracle():
     leaves = amrgen.disk(seed=3, lmax=11, m_thr=2e-4)
     T = amr.Tree(leaves)
     OT = oracle.Tree(leaves)
-    for desc in (amrgen.disk_camera(45.0, 96, 80, max_level=11), amrgen.tiny_camera(70, 50, max_level=9)):
+    for desc, lc in ((amrgen.disk_camera(45.0, 96, 80, max_level=11), 9), (amrgen.tiny_camera(70, 50, max_level=9), 9),
+                     (amrgen.disk_camera(45.0, 96, 80, max_level=11), 4), (amrgen.disk_camera(70.0, 150, 90), 4)):
         W, H = desc["W"], desc["H"]
-        lc = 9
+        log("features at level", lc, "of", desc["W"], "x", desc["H"])
         cam = amr.set_camera(desc, T)
         nt = lod.tiles(W, H)
         feat = torch.empty((nt, 32), dtype=torch.int16, device="cuda")
@@ -277,6 +433,67 @@ def test_forced_wrong_levels_are_caught_by_the_audit():
     torch.cuda.synchronize()
     assert torch.equal(out.view(torch.int32), r7.view(torch.int32))
     assert st[2].item() == 0 and st[3].item() == 0
+
+
+@pytest.mark.parametrize("op", ["sum", "max", "wmean"])
+def test_forced_mixed_levels_match_oracle_per_tile(op):
+    """Random forced per-tile levels 0..max_level (below and above the
+    complete base level 7) with no audit: every tile's pixels are the plain
+    render truncated at that tile's level, bit for bit (the same walk), and
+    match the oracle's render at that level (max bit-exact, sum and wmean
+    within the 2e-6 bar)."""
+    import oracle
+    import paper_1210_8014_amd as amr
+    from paper_1210_8014_amd import lod
+    from tests import parity
+
+    leaves = amrgen.disk(seed=6, lmax=14, m_thr=3e-5)
+    T = amr.Tree(leaves)
+    OT = oracle.Tree(leaves)
+    desc = amrgen.disk_camera(60.0, 200, 136, max_level=14)
+    cam = amr.set_camera(desc, T)
+    W, H, n = cam.W, cam.H, cam.W * cam.H
+    nt = lod.tiles(W, H)
+    rng = np.random.default_rng(5)
+    lv = rng.integers(0, cam.max_level + 1, nt)
+    m = lod.LodModel(dict(lod.default_config(), conf_thresh=0.0, audit_frac=0.0), seed=0)
+    o = {"sum": amr.SUM, "max": amr.MAX, "wmean": amr.WMEAN}[op]
+    kw = dict(field=1, weight=0, los=True) if op == "wmean" else {}
+    out = torch.empty(n, device="cuda")
+    aux = torch.empty(n, device="cuda") if op == "wmean" else None
+    ws = torch.empty(lod.workspace_bytes(W, H), dtype=torch.uint8, device="cuda")
+    st = torch.zeros(8, dtype=torch.int64, device="cuda")
+    got_lv = torch.empty(nt, dtype=torch.int8, device="cuda")
+    lod.render_lod(T, cam, o, m, out, ws, st, aux=aux, forced=torch.as_tensor(lv.astype(np.int8), device="cuda"),
+                   tile_levels=got_lv, **kw)
+    torch.cuda.synchronize()
+    assert np.array_equal(got_lv.cpu().numpy().astype(np.int64), lv)
+    s = st.cpu().numpy()
+    assert s[0] == nt and s[2] == 0 and s[3] == 0 and s[4] == int(lv.sum())
+    outn = out.cpu().numpy()
+    auxn = aux.cpu().numpy() if aux is not None else None
+    tx = (W + lod.TILE - 1) // lod.TILE
+    jj, ii = np.divmod(np.arange(n), W)
+    pix_level = lv[(jj // lod.TILE) * tx + ii // lod.TILE]
+    for L in np.unique(pix_level):
+        rays = np.flatnonzero(pix_level == L)
+        dL = dict(desc, max_level=int(L))
+        cL = amr.set_camera(dL, T)
+        plain = torch.empty(n, device="cuda")
+        pa = torch.empty(n, device="cuda") if op == "wmean" else None
+        amr.render(T, cL, o, plain, pa, **kw)
+        torch.cuda.synchronize()
+        assert np.array_equal(outn[rays].view(np.int32), plain.cpu().numpy()[rays].view(np.int32)), L
+        ocam = OT.camera(dL)
+        assert ocam.as_dict() == cL.as_dict()
+        if op == "sum":
+            parity.check_sum(outn[rays], OT.render(ocam, oracle.SUM, rays=rays)["val"], f"level {L}")
+        elif op == "max":
+            parity.check_max(outn[rays], OT.render(ocam, oracle.MAX, rays=rays)["max"], f"level {L}")
+        else:
+            ref = OT.render(ocam, oracle.WMEAN, field=1, weight=0, los=True, rays=rays)
+            parity.check_wmean(outn[rays], auxn[rays], ref, f"level {L}")
+    log(op, "levels", np.bincount(lv, minlength=cam.max_level + 1))
 
 
 def test_training_reduces_loss_and_model_roundtrips(tmp_path):

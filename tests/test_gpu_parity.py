@@ -288,3 +288,31 @@ def test_gpu_rejects_bad_arguments():
         with pytest.raises(amr.AmrError) as e:
             amr.render(R.T, cam, amr.SUM, out, **kw)
         assert e.value.status == 1
+
+
+def test_gpu_distinct_cells_match_oracle():
+    """amr_mark_cells: the distinct cells met by all rays of an image (the
+    basis of the compulsory traffic) equal the set of cells in the oracle's
+    cell sequences; a second image accumulates onto the same bitmap."""
+    import paper_1210_8014_amd as amr
+
+    L = amrgen.scene("tiny")
+    R = _R(L)
+    OT = oracle.Tree(L)
+    d1, d2 = amrgen.tiny_camera(), amrgen.camera("persp", (1.6, -0.7, 1.3), (0.5, 0.5, 0.5), (0, 0, 1), 97, 61,
+                                                 fov_y=0.9, max_level=5)
+    words = (R.T.ncells + 31) // 32
+    bits = torch.zeros(words, dtype=torch.int32, device="cuda")
+    tot = torch.zeros(1, dtype=torch.int64, device="cuda")
+    seen = set()
+    for k, d in enumerate((d1, d2)):
+        cam, ocam = R.camera(d), OT.camera(d)
+        amr.mark_cells(R.T, cam, bits, tot)
+        torch.cuda.synchronize()
+        _, cells, _ = OT.trace(ocam, np.arange(cam.W * cam.H))
+        seen |= set(map(tuple, cells.tolist()))
+        log("image", k, "distinct cells", int(tot.item()), "oracle", len(seen))
+        assert int(tot.item()) == len(seen)
+    # the bitmap holds exactly that many bits
+    b = bits.cpu().numpy().view(np.uint32)
+    assert int(np.unpackbits(b.view(np.uint8)).sum()) == len(seen)

@@ -126,3 +126,40 @@ def test_probe_stats_against_pinned_render(L):
     f = L.tile_features(st, None, 0.5, nt)
     hit = f[:, 15] > 0
     assert np.allclose(f[hit, 2:12].sum(axis=1), 1.0)
+
+
+def test_adam_constant_gradient_closed_form(L):
+    """With a constant gradient g the bias-corrected moments are exactly g
+    and g^2 at every step, so each step moves a parameter by
+    -lr g / (|g| + eps): after t steps p = p0 - t lr g / (|g| + eps)."""
+    rng = np.random.default_rng(3)
+    p0 = rng.normal(size=50)
+    g = rng.normal(size=50) * np.logspace(-6, 2, 50)
+    lr, eps = 3e-3, 1e-8
+    p, m, v = p0.copy(), np.zeros(50), np.zeros(50)
+    for t in range(1, 41):
+        p, m, v = L.adam(p, g, m, v, t, lr, eps=eps)
+        want = p0 - t * lr * g / (np.abs(g) + eps)
+        assert np.allclose(p, want, rtol=1e-12, atol=1e-14), t
+    # the moments themselves: m_t = g (1 - 0.9^t), v_t = g^2 (1 - 0.999^t)
+    assert np.allclose(m, g * (1 - 0.9 ** 40), rtol=1e-12)
+    assert np.allclose(v, g * g * (1 - 0.999 ** 40), rtol=1e-12)
+
+
+def test_adam_alternating_gradient_closed_form(L):
+    """g_k = (-1)^k g: m_t = (1 - b1) (-1)^t g (1 - (-b1)^t) / (1 + b1),
+    v_t = g^2 (1 - b2^t), and the step uses both bias corrections."""
+    b1, b2, lr, eps = 0.9, 0.999, 1e-2, 1e-8
+    g = np.array([0.5, -2.0, 1e-3])
+    p, m, v = np.zeros(3), np.zeros(3), np.zeros(3)
+    want_p = np.zeros(3)
+    for t in range(1, 25):
+        p, m, v = L.adam(p, (-1.0) ** t * g, m, v, t, lr)
+        mt = (1 - b1) * (-1.0) ** t * g * (1 - (-b1) ** t) / (1 + b1)
+        vt = g * g * (1 - b2 ** t)
+        assert np.allclose(m, mt, rtol=1e-12) and np.allclose(v, vt, rtol=1e-12)
+        want_p = want_p - lr * (mt / (1 - b1 ** t)) / (np.sqrt(vt / (1 - b2 ** t)) + eps)
+        assert np.allclose(p, want_p, rtol=1e-12, atol=1e-15)
+    # the first step is -lr sign(g) (up to eps)
+    p1, _, _ = L.adam(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, lr)
+    assert np.allclose(p1, -lr * g / (np.abs(g) + eps), rtol=1e-12)
