@@ -326,8 +326,10 @@ amr_status amr_lod_loss(const float* logits, const int8_t* labels, int64_t n, fl
 amr_status amr_lod_backward(amr_lod_model* m, const uint16_t* feat, const uint16_t* acts, const float* dlogits,
                             int64_t n, uint16_t* dz, amr_stream s);
 amr_status amr_lod_zero_grads(amr_lod_model* m, amr_stream s);
-/* One Adam step (beta 0.9 / 0.999) with the accumulated gradients, which
- * it then clears; refreshes the bf16 weights. */
+/* One Adam step with the accumulated gradients, which it then clears;
+ * refreshes the bf16 weights.  beta1 = 0.9 and beta2 = 0.999 as fp32 values
+ * (0.89999998 and 0.99900001), eps = 1e-8; moments and weights in fp32, the
+ * bias corrections 1 - beta^t in fp64 then rounded to fp32. */
 amr_status amr_lod_adam_step(amr_lod_model* m, float lr, amr_stream s);
 
 /* Training labels: imgs[0..15] are device renders (same camera, same op) at

@@ -985,7 +985,11 @@ amr_status amr_lod_adam_step(amr_lod_model* m, float lr, amr_stream s) {
   if (!m || !(lr > 0.f)) return fail(AMR_EINVAL, "bad argument");
   const float b1 = 0.9f, b2 = 0.999f;
   m->step += 1;
-  const float c1 = 1.f - std::pow(b1, (float)m->step), c2 = 1.f - std::pow(b2, (float)m->step);
+  // bias corrections 1 - beta^t of the fp32 betas the moment updates use,
+  // formed in fp64: in fp32 the difference cancels (1 - 0.999^2 would keep
+  // only 4 correct digits)
+  const float c1 = (float)(1.0 - std::pow((double)b1, (double)m->step));
+  const float c2 = (float)(1.0 - std::pow((double)b2, (double)m->step));
   hipLaunchKernelGGL(k_adam, dim3((kParams + 255) / 256), dim3(256), 0, (hipStream_t)s, m->P, m->G, m->M, m->V,
                      m->Wb, kParams, lr, b1, b2, 1e-8f, c1, c2);
   hipError_t e = hipGetLastError();
