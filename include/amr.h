@@ -358,6 +358,23 @@ amr_status amr_render_lod(const amr_tree* t, const amr_camera* cam, amr_op op, c
                           const int8_t* forced_levels, void* workspace, int64_t workspace_bytes, int64_t* stats,
                           amr_stream s);
 
+/* amr_render_lod without a workspace argument, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the workspace is a fixed device array
+ * of amr_lod_noalloc_max_bytes() bytes (40 MiB) inside the library, one per
+ * GPU, held until the process ends; the call itself allocates nothing.
+ * Same arguments and results as amr_render_lod otherwise (same kernels:
+ * the outputs are bit-identical to amr_render_lod's).  AMR_ECAPACITY when
+ * amr_lod_workspace_bytes(W, H) exceeds that size (2048 x 2048 images fit);
+ * AMR_EHIP if the array's device address cannot be obtained.  Every call on
+ * one GPU shares that GPU's array and leaves its contents there: calls that
+ * overlap in time on one GPU (other streams, other threads) race and must
+ * be serialised by the caller. */
+int64_t amr_lod_noalloc_max_bytes(void);
+amr_status amr_render_lod_noalloc(const amr_tree* t, const amr_camera* cam, amr_op op, const amr_lod_model* m,
+                                  const amr_render_opts* opts, float* out, float* aux, int8_t* tile_levels,
+                                  const int8_t* forced_levels, int64_t* stats, amr_stream s);
+
 /* ---------------------------------------------------------------- debug */
 
 /* Segments (cells met) per ray for every pixel: counts (device int32 H x W,

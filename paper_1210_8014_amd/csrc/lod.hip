@@ -26,6 +26,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "internal.h"
@@ -1029,16 +1031,24 @@ int64_t amr_lod_workspace_bytes(int32_t W, int32_t H) {
   return ws_planes_offset(W, H) + 2 * align256((int64_t)W * H * 4);
 }
 
-amr_status amr_render_lod(const amr_tree* t, const amr_camera* cam, amr_op op, const amr_lod_model* m,
-                          const amr_render_opts* opts, float* out, float* aux, int8_t* tile_levels,
-                          const int8_t* forced_levels, void* workspace, int64_t workspace_bytes, int64_t* stats,
-                          amr_stream s) {
-  amr_status cs = check_render_common(t, cam);
-  if (cs) return cs;
-  if (!m || !out || !workspace || !stats) return fail(AMR_EINVAL, "null argument");
-  if (op != AMR_SUM && op != AMR_MAX && op != AMR_WMEAN) return fail(AMR_EINVAL, "bad op");
-  if (workspace_bytes < amr_lod_workspace_bytes(cam->W, cam->H)) return fail(AMR_ECAPACITY, "workspace too small");
-  if (((uintptr_t)workspace & 255) || ((uintptr_t)stats & 7)) return fail(AMR_EINVAL, "misaligned workspace/stats");
+}  // extern "C"
+
+// Device memory for amr_render_lod_noalloc: a file-scope device array, one
+// copy per GPU, loaded with the code object and held until the process
+// ends.  Host code never passes the array's name to a kernel (on the host
+// it is only a stand-in for the symbol): the device address of each GPU's
+// copy comes from hipGetSymbolAddress, fetched once per device with that
+// device current, and only that address is used.
+static constexpr int64_t kNoAllocScratchBytes = int64_t(40) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+// The LOD render on a workspace that the caller checked for size and
+// alignment (the two entry points below differ only in where it lives).
+amr_status render_lod_on(const amr_tree* t, const amr_camera* cam, amr_op op, const amr_lod_model* m,
+                         const amr_render_opts* opts, float* out, float* aux, int8_t* tile_levels,
+                         const int8_t* forced_levels, void* workspace, int64_t* stats, amr_stream s) {
   amr_render_opts o = opts ? *opts : amr_render_opts{0, 0, 0, -1};
   const int nf = t->info.nfields;
   if (o.field < 0 || o.field + ((op == AMR_WMEAN && o.los_velocity) ? 2 : 0) >= nf)
@@ -1111,6 +1121,71 @@ amr_status amr_render_lod(const amr_tree* t, const amr_camera* cam, amr_op op, c
   }
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? AMR_OK : fail(AMR_EHIP, hipGetErrorString(e));
+}
+
+amr_status check_lod_args(const amr_tree* t, const amr_camera* cam, amr_op op, const amr_lod_model* m,
+                          const float* out, const int64_t* stats) {
+  amr_status cs = check_render_common(t, cam);
+  if (cs) return cs;
+  if (!m || !out || !stats) return fail(AMR_EINVAL, "null argument");
+  if (op != AMR_SUM && op != AMR_MAX && op != AMR_WMEAN) return fail(AMR_EINVAL, "bad op");
+  if ((uintptr_t)stats & 7) return fail(AMR_EINVAL, "misaligned stats");
+  return AMR_OK;
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+amr_status scratch_for_current_device(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(AMR_EHIP, std::string("hipGetDevice failed: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(AMR_EINVAL, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(AMR_EHIP, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return AMR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+amr_status amr_render_lod(const amr_tree* t, const amr_camera* cam, amr_op op, const amr_lod_model* m,
+                          const amr_render_opts* opts, float* out, float* aux, int8_t* tile_levels,
+                          const int8_t* forced_levels, void* workspace, int64_t workspace_bytes, int64_t* stats,
+                          amr_stream s) {
+  amr_status cs = check_lod_args(t, cam, op, m, out, stats);
+  if (cs) return cs;
+  if (!workspace) return fail(AMR_EINVAL, "null workspace");
+  if (workspace_bytes < amr_lod_workspace_bytes(cam->W, cam->H)) return fail(AMR_ECAPACITY, "workspace too small");
+  if ((uintptr_t)workspace & 255) return fail(AMR_EINVAL, "misaligned workspace");
+  return render_lod_on(t, cam, op, m, opts, out, aux, tile_levels, forced_levels, workspace, stats, s);
+}
+
+int64_t amr_lod_noalloc_max_bytes(void) { return kNoAllocScratchBytes; }
+
+amr_status amr_render_lod_noalloc(const amr_tree* t, const amr_camera* cam, amr_op op, const amr_lod_model* m,
+                                  const amr_render_opts* opts, float* out, float* aux, int8_t* tile_levels,
+                                  const int8_t* forced_levels, int64_t* stats, amr_stream s) {
+  amr_status cs = check_lod_args(t, cam, op, m, out, stats);
+  if (cs) return cs;
+  const int64_t need = amr_lod_workspace_bytes(cam->W, cam->H);
+  if (need > kNoAllocScratchBytes)
+    return fail(AMR_ECAPACITY, "image needs " + std::to_string(need) + " bytes of LOD workspace; the fixed " +
+                                   "device scratch of amr_render_lod_noalloc holds " +
+                                   std::to_string(kNoAllocScratchBytes));
+  void* ws = nullptr;
+  cs = scratch_for_current_device(&ws);
+  if (cs) return cs;
+  return render_lod_on(t, cam, op, m, opts, out, aux, tile_levels, forced_levels, ws, stats, s);
 }
 
 }  // extern "C"

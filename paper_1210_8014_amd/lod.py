@@ -46,6 +46,9 @@ _SIGS = {
     "amr_lod_workspace_bytes": (_i64, [_i32, _i32]),
     "amr_render_lod": (_i32, [_vp, ctypes.POINTER(Camera), _i32, _vp, ctypes.POINTER(RenderOpts), _vp, _vp, _vp,
                               _vp, _vp, _i64, _vp, _vp]),
+    "amr_lod_noalloc_max_bytes": (_i64, []),
+    "amr_render_lod_noalloc": (_i32, [_vp, ctypes.POINTER(Camera), _i32, _vp, ctypes.POINTER(RenderOpts), _vp, _vp,
+                                      _vp, _vp, _vp, _vp]),
 }
 _declared = False
 
@@ -169,6 +172,19 @@ def render_lod(tree: Tree, cam: Camera, op: int, model: LodModel, out, workspace
     _check(_lib().amr_render_lod(tree.handle, ctypes.byref(cam), op, model.handle, ctypes.byref(o), _ptr(out),
                                  _ptr(aux), _ptr(tile_levels), _ptr(forced), _ptr(workspace), workspace.numel(),
                                  _ptr(stats), _stream(stream)))
+
+
+def noalloc_max_bytes() -> int:
+    return int(_lib().amr_lod_noalloc_max_bytes())
+
+
+def render_lod_noalloc(tree: Tree, cam: Camera, op: int, model: LodModel, out, stats, aux=None, field: int = 0,
+                       weight: int = 0, los: bool = False, tile_levels=None, forced=None, stream=None):
+    """amr_render_lod_noalloc: the LOD render on the library's fixed device
+    scratch (no workspace argument, no allocation)."""
+    o = RenderOpts(field, weight, int(bool(los)), -1)
+    _check(_lib().amr_render_lod_noalloc(tree.handle, ctypes.byref(cam), op, model.handle, ctypes.byref(o), _ptr(out),
+                                         _ptr(aux), _ptr(tile_levels), _ptr(forced), _ptr(stats), _stream(stream)))
 
 
 # ------------------------------------------------------------- drivers
