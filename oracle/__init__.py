@@ -87,6 +87,10 @@ def _load():
         lib.oc_trace.argtypes = [ctypes.c_void_p, _P(Camera), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                  ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32]
         lib.oc_pixel_ray.argtypes = [_P(Camera), ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
+        lib.oc_slice.argtypes = [ctypes.c_void_p, _P(Camera), ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+                                 ctypes.c_void_p]
+        lib.oc_resolution.argtypes = [ctypes.c_void_p, _P(Camera), ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                      ctypes.c_int32]
         lib.oc_probe_stats.argtypes = [ctypes.c_void_p, _P(Camera), ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
                                        ctypes.c_void_p, ctypes.c_int32]
         _lib = lib
@@ -195,6 +199,28 @@ class Tree:
         if rc != OK:
             raise RuntimeError(f"oracle render failed ({rc})")
         return dict(val=val, max=mx, aux=aux, absf=absf, absdot=absdot, count=cnt)
+
+    def slice(self, cam: Camera, field: int = 0, rays: Optional[np.ndarray] = None) -> np.ndarray:
+        """Slice map of an orthographic record (oc_slice): fp32 value of the
+        truncated cell holding each pixel's point, NaN outside the box."""
+        n = cam.W * cam.H if rays is None else int(len(rays))
+        r = None if rays is None else np.ascontiguousarray(rays, np.int64)
+        out = np.zeros(n, np.float32)
+        rc = _load().oc_slice(self._h, ctypes.byref(cam), field, _ptr(r), n, _ptr(out))
+        if rc != OK:
+            raise ValueError(f"oracle slice failed ({rc})")
+        return out
+
+    def resolution(self, cam: Camera, rays: Optional[np.ndarray] = None, nthreads: int = 0) -> np.ndarray:
+        """Per-pixel local resolution (oc_resolution): chord-weighted mean
+        cell side in pixels at the cell's depth, fp64."""
+        n = cam.W * cam.H if rays is None else int(len(rays))
+        r = None if rays is None else np.ascontiguousarray(rays, np.int64)
+        out = np.zeros(n, np.float64)
+        rc = _load().oc_resolution(self._h, ctypes.byref(cam), _ptr(r), n, _ptr(out), int(nthreads))
+        if rc != OK:
+            raise RuntimeError(f"oracle resolution failed ({rc})")
+        return out
 
     def probe_stats(self, cam: Camera, rays: np.ndarray, field: int = 0, nthreads: int = 0) -> np.ndarray:
         """[n, 16] per-ray statistics for the learned level of detail (see

@@ -586,3 +586,92 @@ int oc_probe_stats(const oc_tree* T, const oc_camera* C, int32_t field, const in
 
 /* The integer ray of a pixel, as the oracle builds it (for the tests). */
 void oc_pixel_ray(const oc_camera* C, int64_t i, int64_t j, int64_t* o, int64_t* d) { pixel_ray(C, i, j, o, d); }
+
+/*
+ * Slice map (Sec. 3: the "Slicemap" tried on the GPU, a simple tree search):
+ * the value of a field on a plane through the volume.  For an orthographic
+ * record the point of pixel (i, j) is the origin of its ray, O + aU + bV (in
+ * 2^-28 box units); out[r] is the stored fp32 value of field `field` of the
+ * cell of the tree truncated at C->max_level that contains the point (cells
+ * are half-open, so a point on a face belongs to the cell above it), found by
+ * descending from the root one level at a time; NaN for points outside the
+ * box.  ray_ids = pixel indices (NULL: all W*H).
+ */
+int oc_slice(const oc_tree* T, const oc_camera* C, int32_t field, const int64_t* ray_ids, int64_t nrays,
+             float* out) {
+  if (!T || !C || !out || C->kind != 1 || field < 0 || field >= T->nfields) return OC_EINVAL;
+  int64_t total = ray_ids ? nrays : (int64_t)C->W * C->H;
+  for (int64_t r = 0; r < total; ++r) {
+    int64_t pix = ray_ids ? ray_ids[r] : r;
+    int64_t p[3], d[3];
+    pixel_ray(C, pix % C->W, pix / C->W, p, d);
+    if (p[0] < 0 || p[1] < 0 || p[2] < 0 || p[0] >= FIX_ONE || p[1] >= FIX_ONE || p[2] >= FIX_ONE) {
+      out[r] = NAN;
+      continue;
+    }
+    int64_t cur = 0;
+    while (T->nodes[cur].state == 2 && T->nodes[cur].level < C->max_level) {
+      int sh = FIX_BITS - 1 - T->nodes[cur].level; /* bit of the point that picks the child */
+      int c = (int)((p[0] >> sh) & 1) | (int)(((p[1] >> sh) & 1) << 1) | (int)(((p[2] >> sh) & 1) << 2);
+      cur = T->nodes[cur].first_child + c;
+    }
+    out[r] = T->v32[(int64_t)field * T->n + cur];
+  }
+  return OC_OK;
+}
+
+/*
+ * Local resolution of the image at each pixel, for the adaptive blur of
+ * Sec. 2.2 (the filter size follows the local resolution of the image): the
+ * chord-weighted mean, over the cells the pixel's ray meets in the truncated
+ * tree, of the cell's side measured in pixels at the cell's depth.  A cell of
+ * side 2^-l met between ray parameters t0 and t1 spans 2^-l / w(t) pixels,
+ * with the pixel spacing w(t) = 2 |U| t 2^-28 at t = (t0 + t1)/2 for a
+ * perspective record (neighbouring pixel rays differ by 2U in direction) and
+ * w = 2 |U| 2^-28 for an orthographic one.  out[r] = sum(chord x 2^-l / w) /
+ * sum(chord); 0 for rays that miss the box.  fp64 from the exact parameters.
+ */
+int oc_resolution(const oc_tree* T, const oc_camera* C, const int64_t* ray_ids, int64_t nrays, double* out,
+                  int32_t nthreads) {
+  if (!T || !C || !out) return OC_EINVAL;
+  int64_t total = ray_ids ? nrays : (int64_t)C->W * C->H;
+  const double U2 = (double)C->U[0] * (double)C->U[0] + (double)C->U[1] * (double)C->U[1] +
+                    (double)C->U[2] * (double)C->U[2];
+  const double w0 = 2.0 * sqrt(U2) * ldexp(1.0, -FIX_BITS);
+  int err = 0;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+#pragma omp parallel
+  {
+    segbuf B = {0, 0, 0};
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t r = 0; r < total; ++r) {
+      int64_t o[3], d[3];
+      if (ray_segments(T, C, ray_ids ? ray_ids[r] : r, &B, o, d)) {
+#pragma omp atomic write
+        err = 1;
+        continue;
+      }
+      double ulen = unit_length(d);
+      double num = 0.0, den = 0.0;
+      for (int64_t k = 0; k < B.n; ++k) {
+        const double l = chord(&B.s[k], ulen);
+        const double side = ldexp(1.0, -T->nodes[B.s[k].node].level);
+        double w = w0;
+        if (C->kind == 0) {
+          const double t0 = (double)B.s[k].t0.num / (double)B.s[k].t0.den;
+          const double t1 = (double)B.s[k].t1.num / (double)B.s[k].t1.den;
+          w = w0 * 0.5 * (t0 + t1);
+        }
+        num += l * side / w;
+        den += l;
+      }
+      out[r] = den > 0.0 ? num / den : 0.0;
+    }
+    free(B.s);
+  }
+  return err ? OC_ENOMEM : OC_OK;
+}
