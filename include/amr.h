@@ -261,6 +261,43 @@ amr_status amr_tune(amr_tree* t, const amr_camera* cam, amr_op op, const amr_ren
  * e.g. from a saved tuning cache. */
 amr_status amr_set_default_variant(amr_tree* t, amr_op op, int32_t v);
 
+/* ------------------------------------------------- after the ray cast */
+
+/* Local resolution of the image (Sec. 2.2: the post-filter's size follows
+ * the local resolution of the image): per pixel, the chord-weighted mean,
+ * over the cells the ray meets in the truncated tree, of the cell side in
+ * pixels at the cell's depth.  A perspective record's pixel spacing at ray
+ * parameter t is 2 |U| t 2^-28 box units (neighbouring pixel rays differ by
+ * 2U), taken at the middle of each cell's chord; an orthographic record's
+ * is 2 |U| 2^-28.  res: device fp32 H x W; 0 for rays that miss the box.
+ * Sums fp32 Kahan-compensated. */
+amr_status amr_render_resolution(const amr_tree* t, const amr_camera* cam, float* res, amr_stream s);
+
+/* Adaptive Gaussian blur (Sec. 2.2) of an image img (device fp32 H x W,
+ * row-major) with standard deviation sigma = kappa * res (pixels) at each
+ * output pixel, res a resolution plane as above.  The filter is a ladder of
+ * 2-D Gaussians of sigma_k = 0.5 x 2^(k/2), k = 0..10, each truncated to the
+ * square of radius ceil(3 sigma_k) and normalised over that square's pixels
+ * inside the image; a pixel takes the blend of the two levels around its
+ * sigma, linear in log2 sigma (below sigma_0, of the image itself and
+ * level 0, linear in sigma; above sigma_10, level 10; sigma <= 0: the image
+ * value).  out: device fp32 H x W, not aliasing img.  workspace: device,
+ * 256-byte aligned, amr_blur_workspace_bytes(W, H) bytes (11 fp32 planes).
+ * Sums in fp64.  AMR_EINVAL on a bad size, kappa < 0, null, misaligned or
+ * aliased buffers; AMR_ECAPACITY on a small workspace. */
+int64_t amr_blur_workspace_bytes(int32_t W, int32_t H);
+amr_status amr_blur_adaptive(const float* img, const float* res, int32_t W, int32_t H, float kappa, float* out,
+                             void* workspace, int64_t workspace_bytes, amr_stream s);
+
+/* Slice map (Sec. 3, the "Slicemap" of the GPU trial: a simple tree
+ * search): for an orthographic record, the value of field `field` of the
+ * cell of the tree truncated at cam->max_level that holds the point
+ * O + aU + bV of each pixel (the origins of its rays; cells half-open, so a
+ * point on a face belongs to the cell above it).  out: device fp32 H x W,
+ * the cell's stored value (bit for bit), NaN for points outside the box.
+ * AMR_EINVAL for a perspective record or a bad field. */
+amr_status amr_slice(const amr_tree* t, const amr_camera* cam, int32_t field, float* out, amr_stream s);
+
 /* ------------------------------------------------------- learned LOD */
 
 /* Learned per-tile level of detail.  Sec. 2 truncates the tree at one

@@ -87,3 +87,21 @@ def adaptive_blur(img: np.ndarray, res: np.ndarray, kappa: float, pixels: Option
         b_hi = img[y, x] if hi < 0 else (b_lo if hi == lo else level_blur_at(img, x, y, hi))
         out[n] = (1.0 - a) * b_lo + a * b_hi
     return out
+
+
+def adaptive_blur_terms(img: np.ndarray, res: np.ndarray, kappa: float, pixels: np.ndarray):
+    """(values, spread) at the given pixels: the filtered value and the
+    spread (max - min) of the image value and the ladder levels from one
+    below to one above the blended pair (the scale on which an error in
+    sigma, or the choice of pair at a level boundary, moves the result)."""
+    H, W = img.shape
+    img = np.asarray(img, np.float64)
+    vals = adaptive_blur(img, res, kappa, pixels)
+    spread = np.zeros(len(pixels))
+    for n, p in enumerate(np.asarray(pixels, np.int64)):
+        y, x = divmod(int(p), W)
+        lo, hi, _ = blend(kappa * float(res[y, x]))
+        ks = range(max(0, lo - 1), min(NLEVELS - 1, max(hi, 0) + 1) + 1)
+        b = [img[y, x]] + [level_blur_at(img, x, y, k) for k in ks]
+        spread[n] = max(b) - min(b)
+    return vals, spread

@@ -186,6 +186,31 @@ def mark_cells(tree: Tree, cam: Camera, bitmap, distinct, stream=None):
     _check(lib().amr_mark_cells(tree.handle, ctypes.byref(cam), _ptr(bitmap), _ptr(distinct), _stream(stream)))
 
 
+def resolution(tree: Tree, cam: Camera, res, stream=None):
+    """Per-pixel local resolution (amr_render_resolution) into ``res``
+    (device fp32 of H*W)."""
+    _check(lib().amr_render_resolution(tree.handle, ctypes.byref(cam), _ptr(res), _stream(stream)))
+    return res
+
+
+def blur_workspace_bytes(W: int, H: int) -> int:
+    return int(lib().amr_blur_workspace_bytes(W, H))
+
+
+def blur_adaptive(img, res, W: int, H: int, kappa: float, out, workspace, stream=None):
+    """Adaptive Gaussian blur (amr_blur_adaptive) of ``img`` with sigma =
+    kappa * res; ``workspace`` a device tensor of blur_workspace_bytes(W, H)."""
+    _check(lib().amr_blur_adaptive(_ptr(img), _ptr(res), W, H, float(kappa), _ptr(out), _ptr(workspace),
+                                   int(workspace.numel() * workspace.element_size()), _stream(stream)))
+    return out
+
+
+def slice_map(tree: Tree, cam: Camera, out, field: int = 0, stream=None):
+    """Slice map (amr_slice) of an orthographic record into ``out``."""
+    _check(lib().amr_slice(tree.handle, ctypes.byref(cam), field, _ptr(out), _stream(stream)))
+    return out
+
+
 def count_rays(tree: Tree, cam: Camera, ray_ids, counts, stream=None):
     _check(lib().amr_count_rays(tree.handle, ctypes.byref(cam), _ptr(ray_ids), int(ray_ids.numel()), _ptr(counts),
                                 _stream(stream)))

@@ -1,0 +1,247 @@
+// post.hip -- HIP kernels for gfx950 around the ray caster: the per-pixel
+// resolution plane and the adaptive Gaussian post-filter of the image
+// (Sec. 2.2: the blur adapts its size to the local resolution of the image,
+// hiding the blocks drawn by coarse cells), and slice maps (Sec. 3: the
+// "Slicemap" tried on the GPU, a simple tree search for the cell holding
+// each point of a plane).
+//
+// Adaptive filter: sigma(p) = kappa r(p) pixels with r the resolution
+// plane.  A ladder of truncated, image-normalised Gaussians of standard
+// deviations sigma_k = 0.5 x 2^(k/2), k = 0..10 (radius ceil(3 sigma_k)),
+// each exactly separable; the output blends the two levels around sigma(p)
+// linearly in log2 sigma (below the first level, with the image itself).
+// Pass 1 filters every image row with every level at once from one staging
+// of the row in LDS; pass 2 filters the columns of the two levels a pixel
+// needs and blends them.  Sums are accumulated in fp64.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+
+#include "internal.h"
+
+namespace amr {
+namespace {
+
+constexpr int kBlurLevels = 11;
+constexpr int kBlurRmax = 48;  // ceil(3 x 16)
+constexpr float kBlurSigma0 = 0.5f;
+constexpr int kRowTile = 256;  // pixels of a row per block of pass 1
+
+struct BlurLadder {
+  int32_t R[kBlurLevels];
+  float w[kBlurLevels][kBlurRmax + 1];  // w[k][d] = exp(-d^2 / (2 sigma_k^2)), d = 0..R[k]
+};
+
+BlurLadder make_ladder() {
+  BlurLadder L;
+  for (int k = 0; k < kBlurLevels; ++k) {
+    const double s = (double)kBlurSigma0 * std::pow(2.0, 0.5 * k);
+    L.R[k] = (int32_t)std::ceil(3.0 * s);
+    for (int d = 0; d <= kBlurRmax; ++d) L.w[k][d] = d <= L.R[k] ? (float)std::exp(-(double)d * d / (2.0 * s * s)) : 0.f;
+  }
+  return L;
+}
+
+__global__ __launch_bounds__(64) void k_resolution(TreeView T, CameraView C, float inv_w0, float* res, int px) {
+  const int lane = threadIdx.x;
+  const int ty = (int)blockIdx.x / px, tx = (int)blockIdx.x - ty * px;
+  const int i = tx * 8 + (lane & 7), j = ty * 8 + (lane >> 3);
+  if (i >= C.W || j >= C.H) return;
+  Ray R;
+  Entry E;
+  float r = 0.0f;
+  if (setup_ray(C, i, j, R, E)) {
+    ResVis v;
+    v.persp = C.kind == 0;
+    walk_fast<ResVis, true>(T, R, E, C.max_level, v);
+    const float L = v.sl - v.cl;
+    if (L > 0.0f) r = (v.sn - v.cn) / L * inv_w0;
+  }
+  res[(int64_t)j * C.W + i] = r;
+}
+
+// Pass 1: h_k(x, y) = sum_d w_k(d) I(x + d, y) / sum_d w_k(d) over the taps
+// inside the row, for every level k; planes h[k][H][W].
+__global__ __launch_bounds__(kRowTile) void k_blur_rows(const float* __restrict__ img, int W, int H, BlurLadder Lad,
+                                                       float* __restrict__ h) {
+  __shared__ float row[kRowTile + 2 * kBlurRmax];
+  const int y = blockIdx.y, x0 = blockIdx.x * kRowTile, t = threadIdx.x;
+  for (int e = t; e < kRowTile + 2 * kBlurRmax; e += kRowTile) {
+    const int x = x0 - kBlurRmax + e;
+    row[e] = (x >= 0 && x < W) ? img[(int64_t)y * W + x] : 0.0f;
+  }
+  __syncthreads();
+  const int x = x0 + t;
+  if (x >= W) return;
+  const int64_t plane = (int64_t)W * H;
+  for (int k = 0; k < kBlurLevels; ++k) {
+    const int R = Lad.R[k];
+    const int lo = x - R < 0 ? -x : -R, hi = x + R >= W ? W - 1 - x : R;
+    double acc = 0.0, nrm = 0.0;
+    for (int d = lo; d <= hi; ++d) {
+      const double wd = (double)Lad.w[k][d < 0 ? -d : d];
+      acc += wd * (double)row[t + kBlurRmax + d];
+      nrm += wd;
+    }
+    h[k * plane + (int64_t)y * W + x] = (float)(acc / nrm);
+  }
+}
+
+// Pass 2: per pixel, the column filter of the levels around sigma(p) and
+// their blend.  Blocks of 64 x 4 pixels: a wave reads 64 consecutive floats
+// of a row per tap.
+__global__ __launch_bounds__(256) void k_blur_cols(const float* __restrict__ img, const float* __restrict__ res,
+                                                  int W, int H, float kappa, BlurLadder Lad,
+                                                  const float* __restrict__ h, float* __restrict__ out) {
+  const int x = blockIdx.x * 64 + (threadIdx.x & 63), y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (x >= W || y >= H) return;
+  const int64_t p = (int64_t)y * W + x, plane = (int64_t)W * H;
+  const float sigma = kappa * res[p];
+  const float I = img[p];
+  int lo, hi;
+  float a;
+  if (!(sigma > 0.0f)) {
+    out[p] = I;
+    return;
+  }
+  if (sigma < kBlurSigma0) {
+    lo = -1;
+    hi = 0;
+    a = sigma / kBlurSigma0;
+  } else {
+    const float u = 2.0f * log2f(sigma / kBlurSigma0);
+    const int k = (int)floorf(u);
+    if (k >= kBlurLevels - 1) {
+      lo = hi = kBlurLevels - 1;
+      a = 0.0f;
+    } else {
+      lo = k;
+      hi = k + 1;
+      a = u - (float)k;
+    }
+  }
+  double b[2];
+  for (int q = 0; q < 2; ++q) {
+    const int k = q == 0 ? lo : hi;
+    if (k < 0) {
+      b[q] = (double)I;
+      continue;
+    }
+    if (q == 1 && hi == lo) {
+      b[1] = b[0];
+      continue;
+    }
+    const int R = Lad.R[k];
+    const int d0 = y - R < 0 ? -y : -R, d1 = y + R >= H ? H - 1 - y : R;
+    const float* col = h + k * plane + x;
+    double acc = 0.0, nrm = 0.0;
+    for (int d = d0; d <= d1; ++d) {
+      const double wd = (double)Lad.w[k][d < 0 ? -d : d];
+      acc += wd * (double)col[(int64_t)(y + d) * W];
+      nrm += wd;
+    }
+    b[q] = acc / nrm;
+  }
+  out[p] = (float)((1.0 - (double)a) * b[0] + (double)a * b[1]);
+}
+
+// Slice map: the cell of the truncated tree holding the point O + aU + bV
+// of each pixel (orthographic record): located like the walk's descent, from
+// the complete base level (Morton index, no memory read) through the
+// (first child, field 0) records.  NaN outside the box.
+__global__ __launch_bounds__(64) void k_slice(TreeView T, CameraView C, int field, float* out, int px) {
+  const int lane = threadIdx.x;
+  const int ty = (int)blockIdx.x / px, tx = (int)blockIdx.x - ty * px;
+  const int i = tx * 8 + (lane & 7), j = ty * 8 + (lane >> 3);
+  if (i >= C.W || j >= C.H) return;
+  const int64_t a = 2 * (int64_t)i + 1 - C.W, b = 2 * (int64_t)j + 1 - C.H;
+  int64_t p[3];
+  bool in = true;
+  for (int k = 0; k < 3; ++k) {
+    p[k] = C.O[k] + a * C.U[k] + b * C.V[k];
+    in = in && p[k] >= 0 && p[k] < kOne;
+  }
+  float v = __builtin_nanf("");
+  if (in) {
+    const int L = C.max_level;
+    const int b0 = T.base < L ? T.base : L;
+    const int sb = kFix - b0;
+    int32_t node = T.off[b0] + (int32_t)morton3((uint32_t)(p[0] >> sb), (uint32_t)(p[1] >> sb), (uint32_t)(p[2] >> sb));
+    int lvl = b0;
+    ChildVal rec = T.cv[(uint32_t)node];
+    while (lvl < L && rec.child >= 0) {
+      ++lvl;
+      const int s = kFix - lvl;
+      const int oct = (int)((p[0] >> s) & 1) | (int)(((p[1] >> s) & 1) << 1) | (int)(((p[2] >> s) & 1) << 2);
+      node = rec.child + oct;
+      rec = T.cv[(uint32_t)node];
+    }
+    v = field == 0 ? rec.v0 : T.val[(int64_t)field * T.ncells + (uint32_t)node];
+  }
+  out[(int64_t)j * C.W + i] = v;
+}
+
+int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
+
+}  // namespace
+}  // namespace amr
+
+using namespace amr;
+
+extern "C" {
+
+amr_status amr_render_resolution(const amr_tree* t, const amr_camera* cam, float* res, amr_stream s) {
+  amr_status st = check_render_common(t, cam);
+  if (st) return st;
+  if (!res || ((uintptr_t)res & 3)) return fail(AMR_EINVAL, "null or misaligned output");
+  double u2 = 0.0;
+  for (int k = 0; k < 3; ++k) u2 += (double)cam->U[k] * (double)cam->U[k];
+  if (!(u2 > 0.0)) return fail(AMR_EINVAL, "zero pixel step");
+  const float inv_w0 = (float)(1.0 / (2.0 * std::sqrt(u2) * 0x1.0p-28));
+  const int px = (cam->W + 7) / 8, py = (cam->H + 7) / 8;
+  hipLaunchKernelGGL(k_resolution, dim3((unsigned)(px * py)), dim3(64), 0, (hipStream_t)s, t->view, camera_view(*cam),
+                     inv_w0, res, px);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? AMR_OK : fail(AMR_EHIP, std::string("resolution launch failed: ") + hipGetErrorString(e));
+}
+
+int64_t amr_blur_workspace_bytes(int32_t W, int32_t H) {
+  if (W < 1 || H < 1) return 0;
+  return kBlurLevels * align256((int64_t)W * H * 4);
+}
+
+amr_status amr_blur_adaptive(const float* img, const float* res, int32_t W, int32_t H, float kappa, float* out,
+                             void* workspace, int64_t workspace_bytes, amr_stream s) {
+  if (!img || !res || !out || !workspace) return fail(AMR_EINVAL, "null argument");
+  if (W < 1 || H < 1 || W > 32768 || H > 32768) return fail(AMR_EINVAL, "bad image size");
+  if (!(kappa >= 0.0f) || !std::isfinite(kappa)) return fail(AMR_EINVAL, "kappa must be finite and >= 0");
+  if (((uintptr_t)img & 3) || ((uintptr_t)res & 3) || ((uintptr_t)out & 3) || ((uintptr_t)workspace & 255))
+    return fail(AMR_EINVAL, "misaligned buffer");
+  if (out == img) return fail(AMR_EINVAL, "out must not alias img");
+  if (workspace_bytes < amr_blur_workspace_bytes(W, H)) return fail(AMR_ECAPACITY, "workspace too small");
+  static const BlurLadder lad = make_ladder();
+  float* h = (float*)workspace;
+  hipStream_t hs = (hipStream_t)s;
+  hipLaunchKernelGGL(k_blur_rows, dim3((unsigned)((W + kRowTile - 1) / kRowTile), (unsigned)H), dim3(kRowTile), 0, hs,
+                     img, W, H, lad, h);
+  hipLaunchKernelGGL(k_blur_cols, dim3((unsigned)((W + 63) / 64), (unsigned)((H + 3) / 4)), dim3(256), 0, hs, img, res,
+                     W, H, kappa, lad, h, out);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? AMR_OK : fail(AMR_EHIP, std::string("blur launch failed: ") + hipGetErrorString(e));
+}
+
+amr_status amr_slice(const amr_tree* t, const amr_camera* cam, int32_t field, float* out, amr_stream s) {
+  amr_status st = check_render_common(t, cam);
+  if (st) return st;
+  if (cam->kind != 1) return fail(AMR_EINVAL, "a slice takes an orthographic record");
+  if (field < 0 || field >= t->info.nfields) return fail(AMR_EINVAL, "field index out of range");
+  if (!out || ((uintptr_t)out & 3)) return fail(AMR_EINVAL, "null or misaligned output");
+  const int px = (cam->W + 7) / 8, py = (cam->H + 7) / 8;
+  hipLaunchKernelGGL(k_slice, dim3((unsigned)(px * py)), dim3(64), 0, (hipStream_t)s, t->view, camera_view(*cam), field,
+                     out, px);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? AMR_OK : fail(AMR_EHIP, std::string("slice launch failed: ") + hipGetErrorString(e));
+}
+
+}  // extern "C"

@@ -503,6 +503,16 @@ template <class V>
 struct TracksCut<V, decltype((void)V::kTrackCut)> {
   static constexpr bool value = V::kTrackCut;
 };
+// Visitors that declare kNeedsParams = true also receive, before seg(), the
+// exact ray parameters of the cell's entry (en / da) and exit (nb / db).
+template <class V, class = void>
+struct NeedsParams {
+  static constexpr bool value = false;
+};
+template <class V>
+struct NeedsParams<V, decltype((void)V::kNeedsParams)> {
+  static constexpr bool value = V::kNeedsParams;
+};
 
 // kShallow: the caller guarantees max_level < kDeepLevel (no fp64 chords).
 template <class Vis, bool kWholeBox = false, bool kShallow = false>
@@ -616,6 +626,7 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
       else
         len = (float)((double)N * R.ulen64 / ((double)E.da * (double)db));
     }
+    if constexpr (NeedsParams<Vis>::value) vis.params(E.en, E.da, nb, db);
     vis.seg(node, lvl, len, E.p[0] >> s, E.p[1] >> s, E.p[2] >> s);
     ++nseg;
     // Next cell's coordinates: tied axes enter at their face exactly
@@ -780,6 +791,30 @@ struct TraceVis {
     out[2] = flip_bits[1] ? (c1 ^ m) : c1;
     out[3] = flip_bits[2] ? (c2 ^ m) : c2;
     out += 4;
+  }
+};
+
+// Local resolution of the image along a ray, for the adaptive blur: the
+// chord-weighted mean of the cell side in units of the pixel spacing at the
+// cell's depth.  A perspective pixel spacing grows with the ray parameter,
+// so each cell's side is divided by the parameter at the middle of its
+// chord, (en/da + nb/db) / 2; the caller divides the result by the spacing
+// at unit parameter (orthographic: the constant spacing).
+struct ResVis {
+  static constexpr bool kNeedsLength = true;
+  static constexpr bool kNeedsParams = true;
+  int persp = 1;
+  float tm = 1.0f;
+  float sn = 0.0f, cn = 0.0f, sl = 0.0f, cl = 0.0f;  // Kahan pairs: sum(len side / t), sum(len)
+  AMR_HD void fetch(int32_t) {}
+  AMR_HD void fetch0(int32_t, float) {}
+  AMR_HD void params(int32_t en, int32_t da, int32_t nb, int32_t db) {
+    if (persp) tm = 0.5f * ((float)en / (float)da + (float)nb / (float)db);
+  }
+  AMR_HD void seg(int32_t, int lvl, float len, int32_t, int32_t, int32_t) {
+    const float side = ldexpf(1.0f, -lvl);  // exact
+    kahan_add(sn, cn, len * side / tm);
+    kahan_add(sl, cl, len);
   }
 };
 

@@ -276,6 +276,23 @@ def test_gpu_deepzoom_full_size_sampled():
         log("  worst sum rel", res["sum"])
     offs, cells = R.trace(cam, rays[::112])
     assert cells[:, 0].max() >= 18
+    # slice maps through core 0 at the full depth and at the camera's level:
+    # a 2048^2 plane 2^-10 box wide (pixel 2^-21 box), every point bit for bit
+    import paper_1210_8014_amd as amr
+
+    tgt = np.array(camd["target"])
+    for ml in (22, 21, 18):
+        sd = amrgen.camera("ortho", tgt, tgt + np.array([0.0, 0.0, 1.0]), (0, 1, 0), 2048, 2048,
+                           ortho_height=2.0 ** -10, max_level=ml)
+        scam, socam = R.camera(sd), OT.camera(sd)
+        assert scam.as_dict() == socam.as_dict()
+        out = torch.empty(2048 * 2048, device="cuda")
+        amr.slice_map(R.T, scam, out)
+        torch.cuda.synchronize()
+        got, ref = out.cpu().numpy(), OT.slice(socam)
+        assert not np.isnan(ref).any()
+        assert np.array_equal(got.view(np.int32), ref.view(np.int32)), ml
+        log("deep-zoom slice at level", ml, "bit-exact;", len(np.unique(ref)), "distinct values")
 
 
 def test_gpu_rejects_bad_arguments():
