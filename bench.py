@@ -17,8 +17,9 @@ and oracle error on a seeded ray sample:
              of sides 512..2048 in one graph launch per op (sum, wmean),
              against the same images as 512 single launches;
   lod        the learned level of detail against the plain render;
-  blur       the adaptive Gaussian post-filter of the headline images;
-  slice      point-location slice maps of the disk.
+  post       (in config) the adaptive Gaussian post-filter of the headline
+             sum images and 4096^2 slice maps of the disk; the deep-zoom
+             leg also times a level-22 slice through core 0.
 
 Roofline figures of a launch: ``frac`` is the measured HBM traffic of the
 kernel (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a device copy of known
@@ -201,6 +202,39 @@ def oracle_errors(ot, descs, images, ops, frac: float = 0.01, seed: int = 11, nt
     return res
 
 
+def blur_oracle_errors(ot, desc, got, kappa, n: int = 40, seed: int = 5):
+    """The adaptive blur of one image against the oracle's own chain (its
+    render, resolution plane and blur) on n seeded pixels: each pixel's
+    window is rendered by the oracle.  Worst relative error, and worst error
+    over the bound the parity test uses (2.5e-6 of the value and level
+    spread, plus 1e-5 of the spread)."""
+    import numpy as np
+
+    import oracle
+    from oracle import post as OP
+
+    cam = ot.camera(desc)
+    W, H = cam.W, cam.H
+    pix = sample_rays(W * H, n / (W * H), seed)
+    res = ot.resolution(cam, rays=pix)
+    worst_rel, worst_bound = 0.0, 0.0
+    for p, r in zip(pix.tolist(), res.tolist()):
+        y, x = divmod(p, W)
+        lo, hi, _ = OP.blend(kappa * r)
+        R = 0 if hi < 0 else OP.radius(min(OP.NLEVELS - 1, hi + 1))
+        x0, x1, y0, y1 = max(0, x - R), min(W - 1, x + R), max(0, y - R), min(H - 1, y + R)
+        ids = np.array([yy * W + xx for yy in range(y0, y1 + 1) for xx in range(x0, x1 + 1)], np.int64)
+        win = ot.render(cam, oracle.SUM, rays=ids)["val"].reshape(y1 - y0 + 1, x1 - x0 + 1)
+        lres = np.zeros_like(win)
+        lres[y - y0, x - x0] = r
+        val, spread = OP.adaptive_blur_terms(win, lres, kappa, np.array([(y - y0) * (x1 - x0 + 1) + (x - x0)]))
+        err = abs(float(got[p]) - val[0])
+        worst_rel = max(worst_rel, err / abs(val[0]) if val[0] != 0 else (0.0 if err == 0 else float("inf")))
+        bound = 2.5e-6 * (abs(val[0]) + spread[0]) + 1e-5 * spread[0]
+        worst_bound = max(worst_bound, err / bound if bound > 0 else (0.0 if err == 0 else float("inf")))
+    return worst_rel, worst_bound
+
+
 # ------------------------------------------------------------------ headline
 
 def leg_disk(args, ctr, stream, ot):
@@ -279,18 +313,91 @@ def leg_disk(args, ctr, stream, ot):
             imgs[(k, "wmean")] = (outs[2 * k + 1].cpu().numpy(),)
         err = oracle_errors(ot(leaves), descs, imgs, ("sum", "wmean"))
         log(f"disk oracle errors: {err}")
+    shapes = {op: amr.batch_configs()[B.config] for op, B in plans.items()}
     for B in plans.values():
         B.close()
+    post = leg_post(args, tree, cams, descs, [outs[2 * k] for k in range(len(cams))], stream, ot, leaves)
     value = 2 * len(cams) * npix / (t_wall / args.steps) / 1e6
     res = dict(value=value, ms_per_step=1e3 * t_wall / args.steps, leaves=int(leaves.n), cells=int(tree.ncells),
-               segs=segs, distinct=distinct, kern=kern, per_image_ms=per_image_ms, err=err,
-               shapes={op: amr.batch_configs()[B.config] for op, B in plans.items()})
+               segs=segs, distinct=distinct, kern=kern, per_image_ms=per_image_ms, err=err, shapes=shapes, post=post)
     return res, leaves, descs, tree
+
+
+def leg_post(args, tree, cams, descs, sums, stream, ot, leaves, kappa: float = 0.5):
+    """The adaptive Gaussian post-filter of the three headline sum images
+    (resolution plane from a walk of its own, then the two-pass ladder blur)
+    and slice maps of the disk (the midplane and a plane through the disk
+    axis, 4096^2, full depth)."""
+    import numpy as np
+    import torch
+
+    import amrgen
+    import paper_1210_8014_amd as amr
+
+    W = H = 2048
+    npix = W * H
+    res = [torch.empty(npix, device="cuda") for _ in cams]
+    blurred = [torch.empty(npix, device="cuda") for _ in cams]
+    ws = torch.empty(amr.blur_workspace_bytes(W, H), dtype=torch.uint8, device="cuda")
+
+    def resolution():
+        for k, c in enumerate(cams):
+            amr.resolution(tree, c, res[k])
+
+    def blur():
+        for k in range(len(cams)):
+            amr.blur_adaptive(sums[k], res[k], W, H, kappa, blurred[k], ws)
+
+    resolution()
+    blur()
+    reps = max(3, args.steps // 2)
+    t_res = sum(timed_events(resolution, reps, stream)) / reps / len(cams)
+    t_blur = sum(timed_events(blur, reps, stream)) / reps / len(cams)
+    out = {"blur": {"what": "adaptive Gaussian blur of each 2048^2 headline sum image, sigma = %.2f x the "
+                            "per-pixel resolution plane (chord-weighted cell side in pixels)" % kappa,
+                    "resolution_ms_per_image": round(t_res * 1e3, 4), "blur_ms_per_image": round(t_blur * 1e3, 4),
+                    "blur_Mpix_per_s": npix / t_blur / 1e6,
+                    # the filter's own bytes: image and resolution plane in, image out
+                    "algorithmic_GBs": 12.0 * npix / t_blur / 1e9,
+                    "hbm_frac_algorithmic": 12.0 * npix / t_blur / 1e9 / HBM_PEAK_GBS}}
+    log(f"blur: resolution {t_res * 1e3:.3f} ms, blur {t_blur * 1e3:.3f} ms per 2048^2 image")
+    if not args.no_oracle:
+        worst = [blur_oracle_errors(ot(leaves), descs[k], blurred[k].cpu().numpy(), kappa) for k in range(len(cams))]
+        out["blur"]["oracle_error"] = {"rel": max(w[0] for w in worst), "over_bound": max(w[1] for w in worst),
+                                       "sample": "40 seeded pixels per image, each pixel's window rendered by "
+                                                 "the oracle"}
+        log(f"blur oracle errors: {out['blur']['oracle_error']}")
+    # slice maps: 4096^2 planes through the box centre, normal to z and to y
+    S = 4096
+    planes = {"midplane": amrgen.camera("ortho", (0.5, 0.5, 0.5), (0.5, 0.5, 1.5), (0, 1, 0), S, S,
+                                        ortho_height=1.0, max_level=16),
+              "vertical": amrgen.camera("ortho", (0.5, 0.5, 0.5), (0.5, 1.5, 0.5), (0, 0, 1), S, S,
+                                        ortho_height=1.0, max_level=16)}
+    sl = torch.empty(S * S, device="cuda")
+    out["slice"] = {}
+    for name, d in planes.items():
+        c = amr.set_camera(d, tree)
+        f = lambda: amr.slice_map(tree, c, sl)
+        f()
+        t = sum(timed_events(f, reps, stream)) / reps
+        out["slice"][name] = {"ms": round(t * 1e3, 4), "Gpoints_per_s": S * S / t / 1e9,
+                              # one 8-byte leaf record read and one value written per point
+                              "algorithmic_GBs": 12.0 * S * S / t / 1e9}
+        if not args.no_oracle:
+            o = ot(leaves)
+            pts = sample_rays(S * S, 0.01, 3)
+            ref = o.slice(o.camera(d), rays=pts)
+            got = sl.cpu().numpy()[pts]
+            out["slice"][name]["oracle_mismatches"] = int(np.sum(got.view(np.int32) != ref.view(np.int32)))
+            out["slice"][name]["oracle_sample"] = "seeded 1% of the points"
+        log(f"slice {name}: {t * 1e3:.3f} ms ({S * S / t / 1e9:.1f} Gpoints/s)")
+    return out
 
 
 # ------------------------------------------------------------------ deep zoom
 
 def leg_deepzoom(args, ctr, stream):
+    import numpy as np
     import torch
 
     import amrgen
@@ -322,14 +429,31 @@ def leg_deepzoom(args, ctr, stream):
                           "roofline": roofline(kname, avg, segs[0] * B_SEG[op] + n * B_PIX[op],
                                                distinct * B_SEG[op], ctr)}
         log(f"deep zoom {op}: {avg * 1e3:.2f} ms ({vname}), {n / avg / 1e6:.0f} Mrays/s")
+    # slice map through core 0 at full depth (level 22), 4096^2 points 2^-9 box wide
+    tgt = desc["target"]
+    sd = amrgen.camera("ortho", tgt, (tgt[0], tgt[1], tgt[2] + 1.0), (0, 1, 0), 4096, 4096, ortho_height=2.0 ** -9,
+                       max_level=22)
+    scam = amr.set_camera(sd, tree)
+    sl = torch.empty(4096 * 4096, device="cuda")
+    f = lambda: amr.slice_map(tree, scam, sl)
+    f()
+    reps = max(3, args.steps // 2)
+    ts = sum(timed_events(f, reps, stream)) / reps
+    res["slice_core0_level22"] = {"ms": round(ts * 1e3, 4), "Gpoints_per_s": 4096 * 4096 / ts / 1e9,
+                                  "algorithmic_GBs": 12.0 * 4096 * 4096 / ts / 1e9}
+    log(f"deep zoom slice: {ts * 1e3:.3f} ms")
     if not args.no_oracle:
         torch.cuda.synchronize()
         import oracle
 
         imgs = {(0, op): (out[op].cpu().numpy(),) for op in out}
+        slv = sl.cpu().numpy()
         tree.close()
         ot = oracle.Tree(leaves)
         res["oracle_error"] = oracle_errors(ot, [desc], imgs, ("sum", "max"))
+        pts = sample_rays(4096 * 4096, 0.01, 4)
+        ref = ot.slice(ot.camera(sd), rays=pts)
+        res["slice_core0_level22"]["oracle_mismatches"] = int(np.sum(slv[pts].view(np.int32) != ref.view(np.int32)))
         ot.close()
         log(f"deep zoom oracle errors: {res['oracle_error']}")
     tree.close()
@@ -605,6 +729,7 @@ def main():
             "launch_shape": disk["shapes"],
             "single_image_ms_per_step": disk["per_image_ms"],
             "oracle_error": disk["err"],
+            "post": disk["post"],
         },
         "roofline": kern[dom]["roofline"],
         "legs": legs,
