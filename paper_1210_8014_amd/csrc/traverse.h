@@ -490,7 +490,8 @@ AMR_HD uint32_t morton_inc(uint32_t m, int k, bool c) {
 //  - visitors that do not use chord lengths skip their arithmetic.
 // kWholeBox: the ray's stop planes are the box faces (R.stop = 2^28 on every
 // axis, as setup_ray leaves them), which makes the end test one comparison.
-// On return E is no longer the entry state of any cell.
+// On return E is no longer the entry state of any cell (and its fields a
+// and exact are not kept up to date).
 // Visitors that declare kTrackCut = true also learn whether the walk
 // stopped its descent at a cell that has children (a cell cut by the level
 // limit).  A walk that cut no cell visited exactly the cells, in the same
@@ -556,10 +557,11 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
       const int s = kFix - lvl;
       node = pfc + (int32_t)(octant_bits(E.p[0], E.p[1], E.p[2], s) ^ (fm & 7u));
     } else {
+      // (pfc and plv keep their old values: after a base-level cell jr is
+      // -1 and never matches; after a deeper one, plv is that cell's parent
+      // level, set by the descent or the sibling step that reached it)
       lvl = b0;
       node = offb + (int32_t)((mb ^ fm) & mask3);
-      pfc = -1;
-      plv = -2;
     }
     AMR_CHECK_CELL(T, node);
     float v0;
@@ -638,6 +640,16 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
     E.p[0] = h0 + (t0 ? 1 : 0);
     E.p[1] = h1 + (t1 ? 1 : 0);
     E.p[2] = h2 + (t2 ? 1 : 0);
+    // the rest of the next cell's entry state, set before the end test so
+    // that both ways out of this iteration carry the same values (a ray that
+    // ends discards them; on return E is not meaningful)
+    ex0 = t0;
+    ex1 = t1;
+    ex2 = t2;
+    E.lam = lvl;
+    E.en = nb;
+    E.da = db;
+    E.inv_da = invb;
     if (kWholeBox) {
       if ((uint32_t)(E.p[0] | E.p[1] | E.p[2]) >= (uint32_t)kOne) break;
     } else {
@@ -648,9 +660,16 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
       // a base-level cell (most cells of a typical tree): every tied axis
       // moves the base cell, and the next cell restarts at the base level
       jr = -1;
-      mb = morton_inc(mb, 0, t0);
-      mb = morton_inc(mb, 1, t1);
-      mb = morton_inc(mb, 2, t2);
+      // one increment along the exit axis; an edge or corner (several tied
+      // axes, rare) moves along every tied axis
+      const uint32_t mk = p2 ? 0x24924924u : (p1 ? 0x12492492u : 0x09249249u);
+      const uint32_t mb0 = mb;
+      mb = bitsel(mk, (mb | ~mk) + 1u, mb);
+      if ((t2 && !p2) || (t1 && !p1 && !p2)) {
+        mb = morton_inc(mb0, 0, t0);
+        mb = morton_inc(mb, 1, t1);
+        mb = morton_inc(mb, 2, t2);
+      }
     } else {
       // a tied axis whose new coordinate at this level, c + 1, ends in r
       // zero bits (the old c in r one-bits) carries r levels up
@@ -673,16 +692,7 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
         mb = morton_inc(mb, 2, (c1 & bmask) == 0);
       }
     }
-    ex0 = t0;
-    ex1 = t1;
-    ex2 = t2;
-    E.lam = lvl;
-    E.a = p2 ? 2 : (p1 ? 1 : 0);
-    E.en = nb;
-    E.da = db;
-    E.inv_da = invb;
   }
-  E.exact = (ex0 ? 1 : 0) | (ex1 ? 2 : 0) | (ex2 ? 4 : 0);
   return nseg;
 }
 
