@@ -505,7 +505,8 @@ struct TracksCut<V, decltype((void)V::kTrackCut)> {
   static constexpr bool value = V::kTrackCut;
 };
 // Visitors that declare kNeedsParams = true also receive, before seg(), the
-// exact ray parameters of the cell's entry (en / da) and exit (nb / db).
+// ray parameters of the cell's entry and exit as exact numerators with the
+// fp32 reciprocals of their denominators (en, 1 / da, nb, 1 / db).
 template <class V, class = void>
 struct NeedsParams {
   static constexpr bool value = false;
@@ -628,7 +629,7 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
       else
         len = (float)((double)N * R.ulen64 / ((double)E.da * (double)db));
     }
-    if constexpr (NeedsParams<Vis>::value) vis.params(E.en, E.da, nb, db);
+    if constexpr (NeedsParams<Vis>::value) vis.params(E.en, E.inv_da, nb, invb);
     vis.seg(node, lvl, len, E.p[0] >> s, E.p[1] >> s, E.p[2] >> s);
     ++nseg;
     // Next cell's coordinates: tied axes enter at their face exactly
@@ -818,14 +819,19 @@ struct ResVis {
   float sn = 0.0f, cn = 0.0f, sl = 0.0f, cl = 0.0f;  // Kahan pairs: sum(len side / t), sum(len)
   AMR_HD void fetch(int32_t) {}
   AMR_HD void fetch0(int32_t, float) {}
-  AMR_HD void params(int32_t en, int32_t da, int32_t nb, int32_t db) {
-    if (persp) tm = 0.5f * ((float)en / (float)da + (float)nb / (float)db);
+  AMR_HD void params(int32_t en, float inv_da, int32_t nb, float inv_db) {
+    if (persp) tm = 0.5f * ((float)en * inv_da + (float)nb * inv_db);
   }
   AMR_HD void seg(int32_t, int lvl, float len, int32_t, int32_t, int32_t) {
     const float side = ldexpf(1.0f, -lvl);  // exact
-    kahan_add(sn, cn, len * side / tm);
+    kahan_add(sn, cn, len * side * rcp(tm));
     kahan_add(sl, cl, len);
   }
+#if defined(__HIP_DEVICE_COMPILE__)
+  __device__ static float rcp(float x) { return __builtin_amdgcn_rcpf(x); }  // 1 ulp
+#else
+  static float rcp(float x) { return 1.0f / x; }
+#endif
 };
 
 // Sets bit `node` of a bitmap for every cell met and counts the bits it
