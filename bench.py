@@ -18,8 +18,9 @@ and oracle error on a seeded ray sample:
              against the same images as 512 single launches;
   lod        the learned level of detail against the plain render;
   post       (in config) the adaptive Gaussian post-filter of the headline
-             sum images and 4096^2 slice maps of the disk; the deep-zoom
-             leg also times a level-22 slice through core 0.
+             sum images and slice maps of the disk (4096^2 midplane, 4096 x
+             2048 vertical plane); the deep-zoom leg also times a 4000^2
+             level-22 slice through core 0.
 
 Roofline figures of a launch: ``frac`` is the measured HBM traffic of the
 kernel (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a device copy of known
@@ -89,25 +90,44 @@ def batch_kernel_name(config: str, op: str) -> str:
     return "k_batch<%d, ...> (%s)" % (code, config)
 
 
-def variant_kernel_name(variant_name: str, op: str) -> str:
+def batch_grid_size(config: str, cams) -> int:
+    """Work-items of a grid batch launch: one block of 64 K threads per 8x8
+    packet of every image."""
+    packets = sum(((c.W + 7) // 8) * ((c.H + 7) // 8) for c in cams)
+    return packets * 64 * (2 if "split2" in config else 1)
+
+
+def variant_kernel(variant_name: str, op: str, max_level: int, W: int, H: int):
+    """(kernel name as rocprofv3 shows it, work-items) of a single-image
+    variant on a W x H image whose fields have the common layout."""
     code = {"sum": 0, "max": 1, "wmean": 2}[op]
+    remap = 2 if variant_name.endswith("center") else (1 if variant_name.endswith("xcdband") else 0)
     if "split" in variant_name:
-        remap = 2 if variant_name.endswith("center") else (1 if variant_name.endswith("xcdband") else 0)
-        k = variant_name.split("split")[1].split("_")[0]
-        return "k_render_split<%d, %s, %d, true>" % (code, k, remap)
-    return "k_render<%d, ...> (%s)" % (code, variant_name)
+        k = int(variant_name.split("split")[1].split("_")[0])
+        std = op == "wmean" or max_level < 18  # walk_span's specialised walk (std_walk)
+        packets = ((W + 7) // 8) * ((H + 7) // 8)
+        return "k_render_split<%d, %d, %d, %s>" % (code, k, remap, "true" if std else "false"), packets * 64 * k
+    pw = int(variant_name[1:].split("x")[0])
+    wpb = int(variant_name.split("_w")[1].split("_")[0])
+    mode = {"base": 0, "stack": 1, "fast": 2}[variant_name.split("_")[2]]
+    packets = ((W + pw - 1) // pw) * ((H + 64 // pw - 1) // (64 // pw))
+    blocks = (packets + wpb - 1) // wpb
+    return "k_render<%d, %d, %d, %d, %d>" % (code, pw, wpb, remap, mode), blocks * 64 * wpb
 
 
-def roofline(kernel: str, avg_s: float, alg_bytes: float, comp_bytes: float, ctr: dict) -> dict:
-    """Roofline figures of one launch (see the module docstring)."""
-    c = ctr.get(kernel)
+def roofline(kernel: str, grid: int, avg_s: float, alg_bytes: float, comp_bytes: float, ctr: dict) -> dict:
+    """Roofline figures of one launch (see the module docstring); the
+    counters are those of the same kernel on the same grid (workload)."""
+    c = ctr.get("%s@%d" % (kernel, grid))
     r = {"bound": "hbm", "kernel": kernel, "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
          "traffic": None, "algorithmic_GBs": alg_bytes / avg_s / 1e9,
          "compulsory_GBs": (comp_bytes / avg_s / 1e9) if comp_bytes else None, "alu": None}
-    if c:
+    if c and "bytes" in c:
         r["traffic"] = c["bytes"]
         r["achieved"] = c["bytes"] / avg_s / 1e9
         r["frac"] = r["achieved"] / HBM_PEAK_GBS
+        r["l2_hit"] = c.get("l2_hit")
+        r["profiled_avg_ms"] = c["trace_avg_s"] * 1e3 if c.get("trace_avg_s") else None
         if c.get("valu"):
             rate = c["valu"] / avg_s
             r["alu"] = {"bound": "alu", "achieved": rate * 64 / 1e12, "peak": VALU_PEAK_WAVE_PER_S * 64 / 1e12,
@@ -298,9 +318,11 @@ def leg_disk(args, ctr, stream, ot):
         avg = sum(durs) / len(durs)
         alg = sum(s * B_SEG[op] + npix * B_PIX[op] for s in segs)
         comp = distinct * (B_SEG[op])
-        kname = batch_kernel_name(amr.batch_configs()[plans[op].config], op)
+        cfg = amr.batch_configs()[plans[op].config]
+        kname = batch_kernel_name(cfg, op)
         kern[op] = {"avg_ms": round(avg * 1e3, 4), "total_s": sum(durs), "mrays": len(cams) * npix / avg / 1e6,
-                    "seg_per_s": sum(segs) / avg, "roofline": roofline(kname, avg, alg, comp, ctr)}
+                    "seg_per_s": sum(segs) / avg,
+                    "roofline": roofline(kname, batch_grid_size(cfg, cams), avg, alg, comp, ctr)}
         log(f"disk {op}: {avg * 1e3:.3f} ms/launch, {kern[op]['mrays']:.0f} Mrays/s, "
             f"{kern[op]['seg_per_s'] / 1e9:.1f} Gseg/s")
     err = None
@@ -316,14 +338,14 @@ def leg_disk(args, ctr, stream, ot):
     shapes = {op: amr.batch_configs()[B.config] for op, B in plans.items()}
     for B in plans.values():
         B.close()
-    post = leg_post(args, tree, cams, descs, [outs[2 * k] for k in range(len(cams))], stream, ot, leaves)
+    post = leg_post(args, tree, cams, descs, [outs[2 * k] for k in range(len(cams))], stream, ot, leaves, ctr)
     value = 2 * len(cams) * npix / (t_wall / args.steps) / 1e6
     res = dict(value=value, ms_per_step=1e3 * t_wall / args.steps, leaves=int(leaves.n), cells=int(tree.ncells),
                segs=segs, distinct=distinct, kern=kern, per_image_ms=per_image_ms, err=err, shapes=shapes, post=post)
     return res, leaves, descs, tree
 
 
-def leg_post(args, tree, cams, descs, sums, stream, ot, leaves, kappa: float = 0.5):
+def leg_post(args, tree, cams, descs, sums, stream, ot, leaves, ctr, kappa: float = 0.5):
     """The adaptive Gaussian post-filter of the three headline sum images
     (resolution plane from a walk of its own, then the two-pass ladder blur)
     and slice maps of the disk (the midplane and a plane through the disk
@@ -360,6 +382,13 @@ def leg_post(args, tree, cams, descs, sums, stream, ot, leaves, kappa: float = 0
                     # the filter's own bytes: image and resolution plane in, image out
                     "algorithmic_GBs": 12.0 * npix / t_blur / 1e9,
                     "hbm_frac_algorithmic": 12.0 * npix / t_blur / 1e9 / HBM_PEAK_GBS}}
+    cr, cc = ctr.get("k_blur_rows@%d" % npix), ctr.get("k_blur_cols@%d" % npix)
+    if cr and cc and "bytes" in cr and "bytes" in cc:
+        tb = cr["bytes"] + cc["bytes"]
+        out["blur"]["traffic"] = tb
+        out["blur"]["dram_GBs"] = tb / t_blur / 1e9
+        out["blur"]["hbm_frac"] = tb / t_blur / 1e9 / HBM_PEAK_GBS
+    out["blur"]["resolution_roofline"] = roofline("k_resolution", npix, t_res, npix * 4.0, 0.0, ctr)
     log(f"blur: resolution {t_res * 1e3:.3f} ms, blur {t_blur * 1e3:.3f} ms per 2048^2 image")
     if not args.no_oracle:
         worst = [blur_oracle_errors(ot(leaves), descs[k], blurred[k].cpu().numpy(), kappa) for k in range(len(cams))]
@@ -371,21 +400,22 @@ def leg_post(args, tree, cams, descs, sums, stream, ot, leaves, kappa: float = 0
     S = 4096
     planes = {"midplane": amrgen.camera("ortho", (0.5, 0.5, 0.5), (0.5, 0.5, 1.5), (0, 1, 0), S, S,
                                         ortho_height=1.0, max_level=16),
-              "vertical": amrgen.camera("ortho", (0.5, 0.5, 0.5), (0.5, 1.5, 0.5), (0, 0, 1), S, S,
-                                        ortho_height=1.0, max_level=16)}
+              "vertical": amrgen.camera("ortho", (0.5, 0.5, 0.5), (0.5, 1.5, 0.5), (0, 0, 1), S, S // 2,
+                                        ortho_height=0.5, max_level=16)}
     sl = torch.empty(S * S, device="cuda")
     out["slice"] = {}
     for name, d in planes.items():
         c = amr.set_camera(d, tree)
+        npt = c.W * c.H
         f = lambda: amr.slice_map(tree, c, sl)
         f()
         t = sum(timed_events(f, reps, stream)) / reps
-        out["slice"][name] = {"ms": round(t * 1e3, 4), "Gpoints_per_s": S * S / t / 1e9,
+        out["slice"][name] = {"points": f"{c.W}x{c.H}", "ms": round(t * 1e3, 4), "Gpoints_per_s": npt / t / 1e9,
                               # one 8-byte leaf record read and one value written per point
-                              "algorithmic_GBs": 12.0 * S * S / t / 1e9}
+                              "roofline": roofline("k_slice", npt, t, 12.0 * npt, 0.0, ctr)}
         if not args.no_oracle:
             o = ot(leaves)
-            pts = sample_rays(S * S, 0.01, 3)
+            pts = sample_rays(npt, 0.01, 3)
             ref = o.slice(o.camera(d), rays=pts)
             got = sl.cpu().numpy()[pts]
             out["slice"][name]["oracle_mismatches"] = int(np.sum(got.view(np.int32) != ref.view(np.int32)))
@@ -423,24 +453,25 @@ def leg_deepzoom(args, ctr, stream):
         f()
         durs = timed_events(f, max(3, args.steps // 2), stream)
         avg = sum(durs) / len(durs)
-        kname = variant_kernel_name(vname, op)
+        kname, grid = variant_kernel(vname, op, cam.max_level, cam.W, cam.H)
         res["ops"][op] = {"avg_ms": round(avg * 1e3, 4), "mrays": n / avg / 1e6, "seg_per_s": segs[0] / avg,
                           "variant": vname,
-                          "roofline": roofline(kname, avg, segs[0] * B_SEG[op] + n * B_PIX[op],
+                          "roofline": roofline(kname, grid, avg, segs[0] * B_SEG[op] + n * B_PIX[op],
                                                distinct * B_SEG[op], ctr)}
         log(f"deep zoom {op}: {avg * 1e3:.2f} ms ({vname}), {n / avg / 1e6:.0f} Mrays/s")
-    # slice map through core 0 at full depth (level 22), 4096^2 points 2^-9 box wide
+    # slice map through core 0 at full depth (level 22), 4000^2 points 2^-9 box wide
+    SZ = 4000
     tgt = desc["target"]
-    sd = amrgen.camera("ortho", tgt, (tgt[0], tgt[1], tgt[2] + 1.0), (0, 1, 0), 4096, 4096, ortho_height=2.0 ** -9,
+    sd = amrgen.camera("ortho", tgt, (tgt[0], tgt[1], tgt[2] + 1.0), (0, 1, 0), SZ, SZ, ortho_height=2.0 ** -9,
                        max_level=22)
     scam = amr.set_camera(sd, tree)
-    sl = torch.empty(4096 * 4096, device="cuda")
+    sl = torch.empty(SZ * SZ, device="cuda")
     f = lambda: amr.slice_map(tree, scam, sl)
     f()
     reps = max(3, args.steps // 2)
     ts = sum(timed_events(f, reps, stream)) / reps
-    res["slice_core0_level22"] = {"ms": round(ts * 1e3, 4), "Gpoints_per_s": 4096 * 4096 / ts / 1e9,
-                                  "algorithmic_GBs": 12.0 * 4096 * 4096 / ts / 1e9}
+    res["slice_core0_level22"] = {"points": f"{SZ}x{SZ}", "ms": round(ts * 1e3, 4), "Gpoints_per_s": SZ * SZ / ts / 1e9,
+                                  "roofline": roofline("k_slice", SZ * SZ, ts, 12.0 * SZ * SZ, 0.0, ctr)}
     log(f"deep zoom slice: {ts * 1e3:.3f} ms")
     if not args.no_oracle:
         torch.cuda.synchronize()
@@ -451,7 +482,7 @@ def leg_deepzoom(args, ctr, stream):
         tree.close()
         ot = oracle.Tree(leaves)
         res["oracle_error"] = oracle_errors(ot, [desc], imgs, ("sum", "max"))
-        pts = sample_rays(4096 * 4096, 0.01, 4)
+        pts = sample_rays(SZ * SZ, 0.01, 4)
         ref = ot.slice(ot.camera(sd), rays=pts)
         res["slice_core0_level22"]["oracle_mismatches"] = int(np.sum(slv[pts].view(np.int32) != ref.view(np.int32)))
         ot.close()
@@ -481,6 +512,7 @@ def leg_batch(args, ctr, stream):
     descs = amrgen.orbit_cameras(64, seed=0, side_lo=512, side_hi=2048, multiple=16, max_level=16)
     cams = [amr.set_camera(d) for d in descs]
     pairs = [(t, c) for t in range(8) for c in range(64)]
+    cams_all = [cams[c] for _, c in pairs]
     rays = sum(cams[c].W * cams[c].H for _, c in pairs)
     tot = torch.zeros(1, dtype=torch.int64, device="cuda")
     segs = 0
@@ -521,8 +553,8 @@ def leg_batch(args, ctr, stream):
         cfg = amr.batch_configs()[B.config]
         res["ops"][op] = {"avg_ms": round(tb * 1e3, 3), "mrays": rays / tb / 1e6, "seg_per_s": segs / tb,
                           "shape": cfg, "per_image_launches_ms": round(ts * 1e3, 3), "speedup_vs_per_image": ts / tb,
-                          "roofline": roofline(batch_kernel_name(cfg, op), tb, segs * B_SEG[op] + rays * B_PIX[op],
-                                               distinct * B_SEG[op], ctr)}
+                          "roofline": roofline(batch_kernel_name(cfg, op), batch_grid_size(cfg, cams_all), tb,
+                                               segs * B_SEG[op] + rays * B_PIX[op], distinct * B_SEG[op], ctr)}
         log(f"batch {op}: {tb * 1e3:.1f} ms per launch ({cfg}), {rays / tb / 1e6:.0f} Mrays/s; "
             f"512 single launches {ts * 1e3:.1f} ms")
         if not args.no_oracle:
