@@ -412,6 +412,104 @@ amr_status amr_render_lod_noalloc(const amr_tree* t, const amr_camera* cam, amr_
                                   const amr_render_opts* opts, float* out, float* aux, int8_t* tile_levels,
                                   const int8_t* forced_levels, int64_t* stats, amr_stream s);
 
+/* ------------------------------------------- trees larger than the GPU */
+
+/* Rendering a tree held in host memory, streamed through the GPU chunk by
+ * chunk.  The paper finds reading the data the dominant cost (Sec. 3) and
+ * notes that the camera's depth bound means not every cell need be read
+ * (Sec. 2); the order of accumulation along a ray is free (Sec. 2.2).
+ *
+ * A plan cuts a host_only tree (amr_build_opts.host_only) into chunks: the
+ * complete subtrees under cells (cubes) of levels 0..base, base = min(the
+ * tree's shallowest leaf level, 10), found by splitting cubes in Morton
+ * order while a subtree holds more than max_chunk_cells cells.  Each chunk
+ * keeps its cells level by level in Morton order with chunk-local
+ * first-child indices, in pinned host memory owned by the plan (the tree is
+ * not retained and may be freed).  The plan also owns two device buffers of
+ * max_chunk_cells cells each, a copy stream and four events.
+ * host_only != 0 builds the chunks in ordinary host memory and nothing on
+ * the device (inspection and CPU tests; such a plan cannot render).
+ * AMR_EINVAL for a tree that is not host_only or max_chunk_cells outside
+ * 1..2^31-1; AMR_ECAPACITY when the subtree of one base-level cell exceeds
+ * max_chunk_cells; AMR_ENOMEM when host (pinned) or device memory runs out. */
+typedef struct amr_stream_plan amr_stream_plan;
+typedef struct {
+  int64_t max_chunk_cells;
+  int32_t host_only;
+  int32_t pad_;
+} amr_stream_opts;
+amr_status amr_stream_plan_create(const amr_tree* host_tree, const amr_stream_opts* opts, amr_stream_plan** out);
+/* Waits for the plan's copies and kernels, then releases it. */
+void amr_stream_plan_free(amr_stream_plan* p);
+
+typedef struct {
+  int32_t nchunks;
+  int32_t min_chunk_level, max_chunk_level;
+  int32_t pad_;
+  int64_t max_chunk_cells;  /* the capacity asked for */
+  int64_t largest_chunk;    /* cells of the largest chunk */
+  int64_t cells;            /* cells over all chunks (levels above a chunk's cube are in none) */
+  int64_t host_bytes;       /* the chunks' host arrays */
+  int64_t device_bytes;     /* the two device buffers (0 for host_only plans) */
+} amr_stream_plan_info_t;
+amr_status amr_stream_plan_info(const amr_stream_plan* p, amr_stream_plan_info_t* out);
+
+/* Chunk i (0 <= i < nchunks, Morton order of the cubes): the cube (level,
+ * ix, iy, iz), its ncells cells and their host arrays: records holds 2
+ * int32 per cell (chunk-local first-child index or -1, and the bits of
+ * field 0 as fp32), values the fields [nfields][ncells], packed fields 0..3
+ * interleaved (4 fp32 per cell) or NULL for trees of fewer than 4 fields.
+ * level_start[l] is the local index of the first cell of level l
+ * (level_start[25] = ncells); off_local[l], for levels level..base, is the
+ * local index that Morton code 0 of level l would have, so the cell of
+ * Morton code m at such a level is off_local[l] + m.  first is the chunk's
+ * offset in the plan's concatenated arrays.  Pointers live as long as the
+ * plan. */
+typedef struct {
+  int32_t level, ix, iy, iz;
+  int64_t ncells;
+  int64_t first;
+  int64_t level_start[26];
+  int32_t off_local[26];
+  const int32_t* records;
+  const float* values;
+  const float* packed;
+} amr_stream_chunk_t;
+amr_status amr_stream_chunk(const amr_stream_plan* p, int32_t i, amr_stream_chunk_t* out);
+
+/* Pixel rectangle rect = {i0, j0, i1, j1} (inclusive) holding every pixel
+ * of cam whose ray can meet chunk i's cube (i1 < i0 when none can): the
+ * rays the streamed render walks for that chunk. */
+amr_status amr_stream_chunk_rect(const amr_stream_plan* p, int32_t i, const amr_camera* cam, int32_t rect[4]);
+
+/* Workspace of amr_render_streamed: 16 bytes per pixel (per-pixel partial
+ * sums), device memory aligned to 256 bytes. */
+int64_t amr_stream_workspace_bytes(int32_t W, int32_t H);
+
+/* amr_render (same op, opts.field / weight_field / los_velocity, outputs and
+ * conventions; opts.variant is ignored) of the plan's tree, streamed: for
+ * each chunk whose rectangle is not empty, in chunk order, the copy stream
+ * copies the chunk's cells of levels down to min(cam->max_level, lmax)
+ * (only the arrays the op reads) into one of the two device buffers, after
+ * the kernel that last read that buffer; stream s waits for the copy and
+ * walks each ray of the rectangle inside the chunk's cube (the ray clipped
+ * exactly to the cube), adding its fp32 Kahan partial sums to the pixel's
+ * (maximum for MAX) in the workspace.  Every cell of the truncated tree at
+ * a chunk's level or deeper lies in one chunk, and its decisions are the
+ * whole ray's, so MAX is bit-identical to amr_render and SUM / WMEAN differ
+ * from it by rounding only.  The calls enqueue work on s and on the plan's
+ * copy stream and return; the outputs are valid once s is synchronised.
+ * One plan renders one image at a time (calls on one plan are ordered by
+ * its events; workspaces must not be shared between calls in flight).
+ * stats: host int64[3] or NULL: chunks walked, bytes copied to the device,
+ * pixels covered by the rectangles.  AMR_EINVAL for a host_only plan, a bad
+ * camera, op or field, misaligned buffers, or cam->max_level shallower than
+ * the plan's deepest chunk level; AMR_ECAPACITY for a small workspace;
+ * AMR_EHIP when a copy or launch fails. */
+amr_status amr_render_streamed(amr_stream_plan* p, const amr_camera* cam, amr_op op, const amr_render_opts* opts,
+                               float* out, float* aux, void* workspace, int64_t workspace_bytes, int64_t* stats,
+                               amr_stream s);
+
 /* ---------------------------------------------------------------- debug */
 
 /* Segments (cells met) per ray for every pixel: counts (device int32 H x W,

@@ -283,6 +283,72 @@ class Batch:
             pass
 
 
+# ------------------------------------------- trees larger than the GPU
+
+class StreamPlan:
+    """A host_only tree cut into chunks for streamed renders
+    (amr_stream_plan_create / amr_render_streamed).  ``tree`` must be built
+    with ``host_only=True``; it may be closed once the plan exists."""
+
+    def __init__(self, tree: Tree, max_chunk_cells: int, host_only: bool = False):
+        o = _abi.StreamOpts(int(max_chunk_cells), int(bool(host_only)), 0)
+        h = ctypes.c_void_p()
+        _check(lib().amr_stream_plan_create(tree.handle, ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self.info = _abi.StreamPlanInfo()
+        _check(lib().amr_stream_plan_info(h, ctypes.byref(self.info)))
+        self.nfields = int(tree.info.nfields)
+
+    @property
+    def nchunks(self) -> int:
+        return int(self.info.nchunks)
+
+    def chunk(self, i: int) -> dict:
+        """Chunk i: cube, level starts, local offsets and numpy views of its
+        host arrays (records as (child int32, field-0 bits) pairs)."""
+        c = _abi.StreamChunk()
+        _check(lib().amr_stream_chunk(self._h, i, ctypes.byref(c)))
+        n = int(c.ncells)
+        rec = np.ctypeslib.as_array(ctypes.cast(c.records, ctypes.POINTER(ctypes.c_int32)), (n, 2))
+        vals = np.ctypeslib.as_array(ctypes.cast(c.values, ctypes.POINTER(ctypes.c_float)), (self.nfields, n))
+        pk = (np.ctypeslib.as_array(ctypes.cast(c.packed, ctypes.POINTER(ctypes.c_float)), (n, 4))
+              if c.packed else None)
+        return dict(level=c.level, ix=c.ix, iy=c.iy, iz=c.iz, ncells=n, first=int(c.first),
+                    level_start=list(c.level_start), off_local=list(c.off_local), records=rec, values=vals, packed=pk)
+
+    def rect(self, i: int, cam: Camera):
+        """(i0, j0, i1, j1) of chunk i for cam (i1 < i0: no pixel)."""
+        r = (ctypes.c_int32 * 4)()
+        _check(lib().amr_stream_chunk_rect(self._h, i, ctypes.byref(cam), r))
+        return tuple(int(v) for v in r)
+
+    @staticmethod
+    def workspace_bytes(W: int, H: int) -> int:
+        return int(lib().amr_stream_workspace_bytes(W, H))
+
+    def render(self, cam: Camera, op: int, out, workspace, aux=None, field: int = 0, weight: int = 0,
+               los: bool = False, stream=None):
+        """Streamed render into ``out``; returns (chunks walked, bytes copied
+        to the device, pixels covered)."""
+        o = RenderOpts(field, weight, int(bool(los)), -1)
+        st = (ctypes.c_int64 * 3)()
+        _check(lib().amr_render_streamed(self._h, ctypes.byref(cam), op, ctypes.byref(o), _ptr(out), _ptr(aux),
+                                         _ptr(workspace), int(workspace.numel() * workspace.element_size()), st,
+                                         _stream(stream)))
+        return int(st[0]), int(st[1]), int(st[2])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().amr_stream_plan_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def batch_configs():
     L = lib()
     return [L.amr_batch_config_name(c).decode() for c in range(L.amr_batch_config_count())]

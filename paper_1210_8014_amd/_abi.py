@@ -46,6 +46,22 @@ class RenderOpts(ctypes.Structure):
     _fields_ = [("field", _i32), ("weight_field", _i32), ("los_velocity", _i32), ("variant", _i32)]
 
 
+class StreamOpts(ctypes.Structure):
+    _fields_ = [("max_chunk_cells", _i64), ("host_only", _i32), ("pad_", _i32)]
+
+
+class StreamPlanInfo(ctypes.Structure):
+    _fields_ = [("nchunks", _i32), ("min_chunk_level", _i32), ("max_chunk_level", _i32), ("pad_", _i32),
+                ("max_chunk_cells", _i64), ("largest_chunk", _i64), ("cells", _i64), ("host_bytes", _i64),
+                ("device_bytes", _i64)]
+
+
+class StreamChunk(ctypes.Structure):
+    _fields_ = [("level", _i32), ("ix", _i32), ("iy", _i32), ("iz", _i32), ("ncells", _i64), ("first", _i64),
+                ("level_start", _i64 * 26), ("off_local", _i32 * 26), ("records", _vp), ("values", _vp),
+                ("packed", _vp)]
+
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "amr_last_error": (ctypes.c_char_p, []),
@@ -80,6 +96,14 @@ SIGNATURES = {
     "amr_tune": (_i32, [_vp, ctypes.POINTER(Camera), _i32, ctypes.POINTER(RenderOpts), _vp, _vp, _vp, _i32,
                         ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_float)]),
     "amr_set_default_variant": (_i32, [_vp, _i32, _i32]),
+    "amr_stream_plan_create": (_i32, [_vp, ctypes.POINTER(StreamOpts), ctypes.POINTER(_vp)]),
+    "amr_stream_plan_free": (None, [_vp]),
+    "amr_stream_plan_info": (_i32, [_vp, ctypes.POINTER(StreamPlanInfo)]),
+    "amr_stream_chunk": (_i32, [_vp, _i32, ctypes.POINTER(StreamChunk)]),
+    "amr_stream_chunk_rect": (_i32, [_vp, _i32, ctypes.POINTER(Camera), ctypes.POINTER(_i32)]),
+    "amr_stream_workspace_bytes": (_i64, [_i32, _i32]),
+    "amr_render_streamed": (_i32, [_vp, ctypes.POINTER(Camera), _i32, ctypes.POINTER(RenderOpts), _vp, _vp, _vp,
+                                   _i64, ctypes.POINTER(_i64), _vp]),
 }
 
 

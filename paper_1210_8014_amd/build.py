@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libamr.so")
-SOURCES = ["render.hip", "batch.hip", "lod.hip", "post.hip", "tree.cpp"]
+SOURCES = ["render.hip", "batch.hip", "lod.hip", "post.hip", "stream.hip", "tree.cpp"]
 HEADERS = ["traverse.h", "internal.h", os.path.join("..", "..", "include", "amr.h")]
 
 HIP_FLAGS = [

@@ -39,6 +39,8 @@ CameraView camera_view(const amr_camera& c);
 // size, maximum level, kind, origin and direction bounds, non-zero
 // orthographic direction).  AMR_EINVAL with a message otherwise.
 amr_status check_render_common(const amr_tree* t, const amr_camera* cam);
+// The camera part of those checks alone.
+amr_status check_camera(const amr_camera* cam);
 
 struct RenderArgs {
   TreeView t;

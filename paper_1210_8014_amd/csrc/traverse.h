@@ -1049,6 +1049,51 @@ AMR_HD bool span_setup(Ray& R, Entry& E, int b0, int K, int w) {
   return span_bounds(R, E, b0, a, lo, hi);
 }
 
+// The part of the ray inside the cube of level `lc` with integer coordinates
+// (cx, cy, cz) (box frame), for walks over one subtree of the tree.  On entry
+// E is the ray's box entry (setup_ray); on return E is the entry point into
+// the cube and R.stop its far faces, so the walk ends on leaving the cube.
+// False when the ray spends no positive length inside it.  Every cell at
+// level lc or deeper lies inside the cube or outside it, so when the walk
+// starts at level lc or deeper (lc <= min(base, max_level)) the cube's
+// cells partition the ray's cells that lie in it, each with the same exact
+// decisions as on the whole ray.
+// In mirrored coordinates a cube covering cells [lo, hi) of an axis covers
+// [2^28 - hi, 2^28 - lo) when that axis is mirrored.  The entry is the
+// latest of the box entry and the crossings of the cube's near faces,
+// compared exactly; the ray is inside iff the entry point lies in the cube.
+AMR_HD bool cube_clip(Ray& R, Entry& E, int lc, int32_t cx, int32_t cy, int32_t cz) {
+  const int sc = kFix - lc;
+  const int32_t cc[3] = {cx, cy, cz};
+  int32_t mlo[3], mhi[3];
+  AMR_UNROLL
+  for (int k = 0; k < 3; ++k) {
+    const int32_t lo = cc[k] << sc, hi = lo + (int32_t(1) << sc);
+    mlo[k] = R.flip[k] ? kOne - hi : lo;
+    mhi[k] = R.flip[k] ? kOne - lo : hi;
+  }
+  // latest near-face crossing beyond the box entry (en / da)
+  int b = -1;
+  int32_t bn = E.en, bd = E.da;
+  AMR_UNROLL
+  for (int k = 0; k < 3; ++k) {
+    const int32_t n = mlo[k] - R.o[k];
+    if (R.d[k] > 0 && n > 0 && mul64(n, bd) > mul64(bn, R.d[k])) {
+      b = k;
+      bn = n;
+      bd = R.d[k];
+    }
+  }
+  if (b >= 0 && !plane_entry(R, b, mlo[b], E)) return false;
+  AMR_UNROLL
+  for (int k = 0; k < 3; ++k)
+    if (E.p[k] < mlo[k] || E.p[k] >= mhi[k]) return false;
+  R.stop[0] = mhi[0];
+  R.stop[1] = mhi[1];
+  R.stop[2] = mhi[2];
+  return true;
+}
+
 // Partial accumulators of one span: sum (s0, c0); maximum s0; weighted mean
 // (s0, c0) = weight, (s1, c1) = weight x value, each a Kahan pair.
 struct Partial {

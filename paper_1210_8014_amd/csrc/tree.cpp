@@ -137,6 +137,11 @@ using namespace amr;
 amr_status amr::check_render_common(const amr_tree* t, const amr_camera* cam) {
   if (!t || !cam) return fail(AMR_EINVAL, "null tree or camera");
   if (t->info.host_only) return fail(AMR_EINVAL, "host_only tree cannot be rendered");
+  return check_camera(cam);
+}
+
+amr_status amr::check_camera(const amr_camera* cam) {
+  if (!cam) return fail(AMR_EINVAL, "null camera");
   if (cam->W < 1 || cam->H < 1 || cam->W > 32768 || cam->H > 32768) return fail(AMR_EINVAL, "bad image size");
   if (cam->max_level < 0 || cam->max_level > kMaxLevel) return fail(AMR_EINVAL, "bad max_level");
   if (cam->kind != 0 && cam->kind != 1) return fail(AMR_EINVAL, "bad camera kind");

@@ -122,3 +122,83 @@ class EmuTree:
         cells = np.zeros((max(int(offs[-1]), 1), 4), np.int32)
         _load().emu_render_split(*self._tree_args(), *args, None, None, None, _p(offs), _p(cells), *tail)
         return out, aux, cnt, (offs, cells[:int(offs[-1])])
+
+
+class EmuStream:
+    """The streamed render over a library stream plan's chunk arrays, on the
+    CPU: each chunk's rays clipped to its cube and walked by the traversal
+    core, partials merged in chunk order (as the streamed kernels do)."""
+
+    def __init__(self, plan, tree):
+        info = tree.info
+        self.plan = plan
+        self.base = min(int(info.levelmin), 10)
+        self.lmax = int(info.lmax)
+        self.nfields = int(info.nfields)
+        self.chunks = [plan.chunk(i) for i in range(plan.nchunks)]
+
+    def _chunk_call(self, c, cam, op, field, weight, los, ml, pix, acc, counts, entry, offsets=None, cells=None):
+        k4, ofuv = _cam_args(cam)
+        off = np.array(c["off_local"], np.int32)
+        _load().emu_stream_chunk(
+            _p(c["records"]), _p(c["values"]), _p(c["packed"]), ctypes.c_int64(c["ncells"]),
+            ctypes.c_int32(self.nfields), ctypes.c_int32(self.base), ctypes.c_int32(self.lmax), _p(off),
+            ctypes.c_int32(c["level"]), ctypes.c_int32(c["ix"]), ctypes.c_int32(c["iy"]), ctypes.c_int32(c["iz"]),
+            _p(k4), _p(ofuv), ctypes.c_int32(op), ctypes.c_int32(field), ctypes.c_int32(weight),
+            ctypes.c_int32(int(los)), ctypes.c_int32(ml), _p(pix), ctypes.c_int64(len(pix)), _p(acc), _p(counts),
+            _p(entry), _p(offsets), _p(cells))
+
+    def render(self, cam, op, field=0, weight=0, los=False, rays=None, check_rects=True):
+        """(out, aux, counts); with check_rects, every ray that meets a
+        chunk's cube must lie in the plan's pixel rectangle of that chunk."""
+        n = cam.W * cam.H if rays is None else len(rays)
+        pix = np.arange(n, dtype=np.int64) if rays is None else np.ascontiguousarray(rays, np.int64)
+        acc = np.zeros((n, 4), np.float32)
+        if op == 1:
+            acc[:, 0] = -np.inf
+        cnt = np.zeros(n, np.int32)
+        for k, c in enumerate(self.chunks):
+            entry = np.zeros(2 * n, np.int64)
+            self._chunk_call(c, cam, op, field, weight, los, cam.max_level, pix, acc, cnt, entry)
+            if check_rects:
+                hit = entry[1::2] != 0
+                i0, j0, i1, j1 = self.plan.rect(k, cam)
+                pi, pj = pix % cam.W, pix // cam.W
+                inside = (pi >= i0) & (pi <= i1) & (pj >= j0) & (pj <= j1)
+                assert not (hit & ~inside).any(), f"chunk {k} rectangle misses rays"
+        out = np.zeros(n, np.float32)
+        aux = np.zeros(n, np.float32)
+        _load().emu_stream_finish(ctypes.c_int32(op), _p(acc), ctypes.c_int64(n), _p(out), _p(aux))
+        return out, aux, cnt
+
+    def trace(self, cam, rays):
+        """Cells of each ray: every chunk's piece, pieces ordered along the
+        ray by their exact entry parameter."""
+        from fractions import Fraction
+
+        pix = np.ascontiguousarray(rays, np.int64)
+        n = len(pix)
+        pieces = [[] for _ in range(n)]
+        for c in self.chunks:
+            acc = np.zeros((n, 4), np.float32)
+            cnt = np.zeros(n, np.int32)
+            entry = np.zeros(2 * n, np.int64)
+            self._chunk_call(c, cam, 1, 0, 0, False, cam.max_level, pix, acc, cnt, entry)
+            offs = np.zeros(n + 1, np.int64)
+            offs[1:] = np.cumsum(cnt)
+            cells = np.zeros((max(int(offs[-1]), 1), 4), np.int32)
+            cnt2 = np.zeros(n, np.int32)
+            self._chunk_call(c, cam, 1, 0, 0, False, cam.max_level, pix, acc, cnt2, entry, offs, cells)
+            for r in range(n):
+                if entry[2 * r + 1]:
+                    pieces[r].append((Fraction(int(entry[2 * r]), int(entry[2 * r + 1])), cells[offs[r]:offs[r + 1]]))
+        out_offs = np.zeros(n + 1, np.int64)
+        seqs = []
+        for r in range(n):
+            ps = sorted(pieces[r], key=lambda q: q[0])
+            assert all(ps[k][0] < ps[k + 1][0] for k in range(len(ps) - 1)), "two pieces enter at one point"
+            s = np.concatenate([q[1] for q in ps]) if ps else np.zeros((0, 4), np.int32)
+            seqs.append(s)
+            out_offs[r + 1] = out_offs[r] + len(s)
+        cells = np.concatenate(seqs) if int(out_offs[-1]) else np.zeros((0, 4), np.int32)
+        return out_offs, cells

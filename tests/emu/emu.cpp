@@ -230,3 +230,90 @@ extern "C" int emu_render_cut(const int32_t* child, const float* val, int64_t nc
 extern "C" void emu_div_q28(const int64_t* num, const int32_t* d, int32_t* q, int64_t n) {
   for (int64_t r = 0; r < n; ++r) q[r] = div_q28(num[r], d[r]);
 }
+
+// One chunk of the streamed render (the library's plan arrays: 8-byte
+// records with chunk-local first-child indices, fields [nfields][ncells],
+// interleaved records or null, local level offsets): every ray of pix is
+// clipped to the chunk's cube and its piece walked as the streamed kernel
+// walks it, the partial merged into acc (4 floats per ray).  counts[r] is
+// increased by the piece's cells; entry[2r..] receives the piece's entry
+// parameter (numerator, denominator) or (0, 0) without a piece; with
+// offsets, the piece's cells go to cells + 4 offsets[r].
+template <int OP, bool kStd>
+static void chunk_pixel(const TreeView& T, const CameraView& C, int field, int wfield, int los, int ml, int lc,
+                        int cx, int cy, int cz, int i, int j, float* acc, int32_t* count, int64_t* entry,
+                        int32_t* cells) {
+  Ray R;
+  Entry E;
+  entry[0] = entry[1] = 0;
+  if (!setup_ray(C, i, j, R, E) || !cube_clip(R, E, lc, cx, cy, cz)) return;
+  entry[0] = E.en;
+  entry[1] = E.da;
+  const Entry E0 = E;
+  Partial P;
+  partial_init<OP>(P);
+  walk_span<OP, false, false, kStd>(T, R, E, ml, field, wfield, los, P);
+  Partial A{acc[0], acc[1], acc[2], acc[3]};
+  partial_merge<OP>(A, P);
+  acc[0] = A.s0;
+  acc[1] = A.c0;
+  acc[2] = A.s1;
+  acc[3] = A.c1;
+  CountVis cv;
+  E = E0;
+  *count += walk_fast<CountVis>(T, R, E, ml, cv);
+  if (cells) {
+    TraceVis tv;
+    tv.out = cells;
+    for (int k = 0; k < 3; ++k) tv.flip_bits[k] = R.flip[k] ? 1 : 0;
+    E = E0;
+    walk_fast<TraceVis>(T, R, E, ml, tv);
+  }
+}
+
+extern "C" int emu_stream_chunk(const int32_t* records, const float* values, const float* packed, int64_t ncells,
+                                int32_t nfields, int32_t base, int32_t lmax, const int32_t* off_local, int32_t lc,
+                                int32_t cx, int32_t cy, int32_t cz, const int32_t* cam4, const int64_t* ofuv,
+                                int32_t op, int32_t field, int32_t wfield, int32_t los, int32_t max_level,
+                                const int64_t* pix, int64_t n, float* acc, int32_t* counts, int64_t* entry,
+                                const int64_t* offsets, int32_t* cells) {
+  TreeView T{};
+  T.cv = (const ChildVal*)records;
+  T.child = nullptr;
+  T.val = values;
+  T.ncells = ncells;
+  T.nfields = nfields;
+  T.base = base;
+  T.lmax = lmax;
+  for (int l = 0; l < kMaxLevel + 2; ++l) T.off[l] = off_local[l];
+  const bool pk = op == kOpWMean && los && wfield == 0 && field == 1 && packed;
+  T.packed = pk ? (const Cell4*)packed : nullptr;
+  const CameraView C = make_cam(cam4, ofuv);
+  const bool sw = std_walk(op, T, field, wfield, los, max_level);
+  par(n, [&](int64_t r) {
+    const int i = (int)(pix[r] % C.W), j = (int)(pix[r] / C.W);
+    float* a = acc + 4 * r;
+    int32_t* cc = cells ? cells + 4 * offsets[r] : nullptr;
+    int64_t* en = entry + 2 * r;
+#define AMR_EMU_CHUNK(OPV, S) \
+  chunk_pixel<OPV, S>(T, C, field, wfield, los, max_level, lc, cx, cy, cz, i, j, a, counts + r, en, cc)
+    if (op == 0) sw ? AMR_EMU_CHUNK(kOpSum, true) : AMR_EMU_CHUNK(kOpSum, false);
+    else if (op == 1) sw ? AMR_EMU_CHUNK(kOpMax, true) : AMR_EMU_CHUNK(kOpMax, false);
+    else sw ? AMR_EMU_CHUNK(kOpWMean, true) : AMR_EMU_CHUNK(kOpWMean, false);
+#undef AMR_EMU_CHUNK
+  });
+  return 0;
+}
+
+// Final values of streamed partials (acc: 4 floats per ray).
+extern "C" void emu_stream_finish(int32_t op, const float* acc, int64_t n, float* out, float* aux) {
+  for (int64_t r = 0; r < n; ++r) {
+    const Partial P{acc[4 * r], acc[4 * r + 1], acc[4 * r + 2], acc[4 * r + 3]};
+    float o = 0.0f, x = 0.0f;
+    if (op == 0) partial_finish<kOpSum>(P, o, x);
+    else if (op == 1) partial_finish<kOpMax>(P, o, x);
+    else partial_finish<kOpWMean>(P, o, x);
+    out[r] = o;
+    aux[r] = x;
+  }
+}
