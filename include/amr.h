@@ -425,18 +425,19 @@ amr_status amr_render_lod_noalloc(const amr_tree* t, const amr_camera* cam, amr_
  * order while a subtree holds more than max_chunk_cells cells.  Each chunk
  * keeps its cells level by level in Morton order with chunk-local
  * first-child indices, in pinned host memory owned by the plan (the tree is
- * not retained and may be freed).  The plan also owns two device buffers of
- * max_chunk_cells cells each, a copy stream and four events.
+ * not retained and may be freed).  The plan also owns nbuffers device
+ * buffers of max_chunk_cells cells each, a copy stream and two events per
+ * buffer.
  * host_only != 0 builds the chunks in ordinary host memory and nothing on
  * the device (inspection and CPU tests; such a plan cannot render).
- * AMR_EINVAL for a tree that is not host_only or max_chunk_cells outside
- * 1..2^31-1; AMR_ECAPACITY when the subtree of one base-level cell exceeds
+ * AMR_EINVAL for a tree that is not host_only, max_chunk_cells outside
+ * 1..2^31-1 or nbuffers outside 0, 2..8; AMR_ECAPACITY when the subtree of one base-level cell exceeds
  * max_chunk_cells; AMR_ENOMEM when host (pinned) or device memory runs out. */
 typedef struct amr_stream_plan amr_stream_plan;
 typedef struct {
   int64_t max_chunk_cells;
   int32_t host_only;
-  int32_t pad_;
+  int32_t nbuffers;  /* device buffers the chunks rotate through: 2..8, 0 = 4 */
 } amr_stream_opts;
 amr_status amr_stream_plan_create(const amr_tree* host_tree, const amr_stream_opts* opts, amr_stream_plan** out);
 /* Waits for the plan's copies and kernels, then releases it. */
@@ -445,12 +446,12 @@ void amr_stream_plan_free(amr_stream_plan* p);
 typedef struct {
   int32_t nchunks;
   int32_t min_chunk_level, max_chunk_level;
-  int32_t pad_;
+  int32_t nbuffers;
   int64_t max_chunk_cells;  /* the capacity asked for */
   int64_t largest_chunk;    /* cells of the largest chunk */
   int64_t cells;            /* cells over all chunks (levels above a chunk's cube are in none) */
   int64_t host_bytes;       /* the chunks' host arrays */
-  int64_t device_bytes;     /* the two device buffers (0 for host_only plans) */
+  int64_t device_bytes;     /* the device buffers (0 for host_only plans) */
 } amr_stream_plan_info_t;
 amr_status amr_stream_plan_info(const amr_stream_plan* p, amr_stream_plan_info_t* out);
 
@@ -482,25 +483,30 @@ amr_status amr_stream_chunk(const amr_stream_plan* p, int32_t i, amr_stream_chun
  * rays the streamed render walks for that chunk. */
 amr_status amr_stream_chunk_rect(const amr_stream_plan* p, int32_t i, const amr_camera* cam, int32_t rect[4]);
 
-/* Workspace of amr_render_streamed: 16 bytes per pixel (per-pixel partial
- * sums), device memory aligned to 256 bytes. */
+/* Workspace of amr_render_streamed: 32 bytes per pixel (two planes of
+ * per-pixel partial sums), device memory aligned to 256 bytes. */
 int64_t amr_stream_workspace_bytes(int32_t W, int32_t H);
 
 /* amr_render (same op, opts.field / weight_field / los_velocity, outputs and
  * conventions; opts.variant is ignored) of the plan's tree, streamed: for
  * each chunk whose rectangle is not empty, in chunk order, the copy stream
  * copies the chunk's cells of levels down to min(cam->max_level, lmax)
- * (only the arrays the op reads) into one of the two device buffers, after
- * the kernel that last read that buffer; stream s waits for the copy and
- * walks each ray of the rectangle inside the chunk's cube (the ray clipped
- * exactly to the cube), adding its fp32 Kahan partial sums to the pixel's
- * (maximum for MAX) in the workspace.  Every cell of the truncated tree at
- * a chunk's level or deeper lies in one chunk, and its decisions are the
- * whole ray's, so MAX is bit-identical to amr_render and SUM / WMEAN differ
- * from it by rounding only.  The calls enqueue work on s and on the plan's
- * copy stream and return; the outputs are valid once s is synchronised.
- * One plan renders one image at a time (calls on one plan are ordered by
- * its events; workspaces must not be shared between calls in flight).
+ * (only the arrays the op reads) into the next of the plan's device
+ * buffers in turn, after the kernel that last read that buffer; then the
+ * chunk's kernel walks each ray of the rectangle inside the chunk's cube
+ * (the ray clipped exactly to the cube) and adds its fp32 Kahan partial
+ * sums to the pixel's (maximum for MAX).  Chunks alternate between stream s
+ * (first plane of the workspace) and the plan's second compute stream
+ * (second plane), so that kernels overlap; at the end s merges the second
+ * plane into the first, pixel by pixel, and writes the outputs.  Every cell
+ * of the truncated tree at a chunk's level or deeper lies in one chunk, and
+ * its decisions are the whole ray's, so MAX is bit-identical to amr_render
+ * and SUM / WMEAN differ from it by rounding only; the order of the sums
+ * depends on the chunk order and the camera alone, so results are
+ * deterministic.  The calls enqueue work on s and on the plan's streams and
+ * return; the outputs are valid once s is synchronised.  One plan renders
+ * one image at a time (calls on one plan are ordered by its events;
+ * workspaces must not be shared between calls in flight).
  * stats: host int64[3] or NULL: chunks walked, bytes copied to the device,
  * pixels covered by the rectangles.  AMR_EINVAL for a host_only plan, a bad
  * camera, op or field, misaligned buffers, or cam->max_level shallower than

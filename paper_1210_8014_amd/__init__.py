@@ -290,8 +290,8 @@ class StreamPlan:
     (amr_stream_plan_create / amr_render_streamed).  ``tree`` must be built
     with ``host_only=True``; it may be closed once the plan exists."""
 
-    def __init__(self, tree: Tree, max_chunk_cells: int, host_only: bool = False):
-        o = _abi.StreamOpts(int(max_chunk_cells), int(bool(host_only)), 0)
+    def __init__(self, tree: Tree, max_chunk_cells: int, host_only: bool = False, nbuffers: int = 0):
+        o = _abi.StreamOpts(int(max_chunk_cells), int(bool(host_only)), int(nbuffers))
         h = ctypes.c_void_p()
         _check(lib().amr_stream_plan_create(tree.handle, ctypes.byref(o), ctypes.byref(h)))
         self._h = h

@@ -47,11 +47,11 @@ class RenderOpts(ctypes.Structure):
 
 
 class StreamOpts(ctypes.Structure):
-    _fields_ = [("max_chunk_cells", _i64), ("host_only", _i32), ("pad_", _i32)]
+    _fields_ = [("max_chunk_cells", _i64), ("host_only", _i32), ("nbuffers", _i32)]
 
 
 class StreamPlanInfo(ctypes.Structure):
-    _fields_ = [("nchunks", _i32), ("min_chunk_level", _i32), ("max_chunk_level", _i32), ("pad_", _i32),
+    _fields_ = [("nchunks", _i32), ("min_chunk_level", _i32), ("max_chunk_level", _i32), ("nbuffers", _i32),
                 ("max_chunk_cells", _i64), ("largest_chunk", _i64), ("cells", _i64), ("host_bytes", _i64),
                 ("device_bytes", _i64)]
 

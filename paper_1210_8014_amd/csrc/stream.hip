@@ -7,9 +7,10 @@
 // tree's complete base level (a cube of the box), stored with chunk-local
 // indices in pinned host memory.  A render streams the chunks that the
 // camera sees, only their levels down to the camera's maximum level, through
-// two device buffers on a copy stream, while the compute stream walks every
-// ray's part inside the previous chunk's cube and adds it to per-pixel
-// Kahan partials (the maximum for MAX).  Each cell lies in exactly one cube
+// a few device buffers on a copy stream, while two compute streams take the
+// copied chunks in turn, walk every ray's part inside the chunk's cube and
+// add it to per-pixel Kahan partials (the maximum for MAX), one plane of
+// partials per compute stream, merged at the end.  Each cell lies in exactly one cube
 // and is decided exactly as on the whole ray, so MAX is bit-identical to
 // the in-memory render and SUM / WMEAN differ from it by rounding only.
 #include <hip/hip_runtime.h>
@@ -38,6 +39,7 @@ struct Chunk {
 };
 
 constexpr int64_t kAlign = 256;
+constexpr int kMaxBuffers = 8;
 int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 template <class F>
@@ -73,12 +75,15 @@ struct amr_stream_plan {
   ChildVal* cv = nullptr;  // [total]
   Cell4* packed = nullptr; // [total] when nfields >= 4
   float* val = nullptr;    // chunk by chunk: [nfields][chunk ncells]
-  // device side
-  char* slot[2] = {nullptr, nullptr};
+  // device side: nslots buffers of cap cells, used in turn
+  int32_t nslots = 0;
+  char* slot[kMaxBuffers] = {};
   int64_t slot_bytes = 0, off_packed = 0, off_val = 0;
   hipStream_t copy = nullptr;
-  hipEvent_t copied[2] = {nullptr, nullptr}, consumed[2] = {nullptr, nullptr};
-  bool used[2] = {false, false};
+  hipStream_t compute2 = nullptr;  // the second compute stream (plane B)
+  hipEvent_t started = nullptr, finished2 = nullptr;
+  hipEvent_t copied[kMaxBuffers] = {}, consumed[kMaxBuffers] = {};
+  bool used[kMaxBuffers] = {};
 };
 
 namespace {
@@ -99,12 +104,15 @@ void* host_alloc(amr_stream_plan* p, size_t bytes) {
 }
 
 void release(amr_stream_plan* p) {
-  for (int s = 0; s < 2; ++s) {
+  for (int s = 0; s < kMaxBuffers; ++s) {
     if (p->slot[s]) (void)hipFree(p->slot[s]);
     if (p->copied[s]) (void)hipEventDestroy(p->copied[s]);
     if (p->consumed[s]) (void)hipEventDestroy(p->consumed[s]);
   }
+  if (p->started) (void)hipEventDestroy(p->started);
+  if (p->finished2) (void)hipEventDestroy(p->finished2);
   if (p->copy) (void)hipStreamDestroy(p->copy);
+  if (p->compute2) (void)hipStreamDestroy(p->compute2);
   host_free(p, p->cv);
   host_free(p, p->packed);
   host_free(p, p->val);
@@ -114,13 +122,19 @@ void release(amr_stream_plan* p) {
 // Pixel rectangle [i0, i1] x [j0, j1] that holds every pixel whose ray can
 // meet the chunk's cube; false when none can.  A point x lies on the ray of
 // (a, b) iff x - O = t (F + a U + b V) (perspective, t > 0) or
-// x - O = a U + b V + t F (orthographic); solving that 3 x 3 system at the
-// cube's corners bounds (a, b) over the cube, whose image is the convex hull
-// of the corners' images when every corner lies in front of a perspective
-// eye.  Otherwise, or for a nearly singular record, the whole image.  The
-// bounds widen by one pixel, far beyond the fp64 rounding, so the rectangle
-// is conservative; rays inside it that miss the cube are rejected exactly
-// by the kernel.
+// x - O = a U + b V + t F (orthographic); solving that 3 x 3 system gives
+// (t, a, b) of any point, and the image of a convex set under (a, b) is the
+// convex hull of its vertices' images (for a perspective record, where t > 0
+// on the whole set).  Perspective: no ray of the image meets the cube before
+// t_min = d / (2 Dmax), d the distance from the eye to the cube and Dmax a
+// bound on the length of every pixel's direction, since by then a ray is
+// closer to the eye than d; so the cube is cut by the plane t = t_min, and
+// its part beyond is the convex polytope whose vertices are the corners
+// beyond the plane and the crossings of the plane by the cube's edges.  An
+// eye inside the cube, or a nearly singular record, gives the whole image.
+// The bounds widen by one pixel, far beyond the fp64 rounding, so the
+// rectangle is conservative; rays inside it that miss the cube are rejected
+// exactly by the kernel.
 bool chunk_rect(const amr_camera& cam, const Chunk& c, int32_t r[4]) {
   const int W = cam.W, H = cam.H;
   r[0] = 0;
@@ -147,33 +161,57 @@ bool chunk_rect(const amr_camera& cam, const Chunk& c, int32_t r[4]) {
   inv[2][1] = M[0][1] * M[2][0] - M[0][0] * M[2][1];
   inv[2][2] = M[0][0] * M[1][1] - M[0][1] * M[1][0];
   const double det = M[0][0] * inv[0][0] + M[0][1] * inv[1][0] + M[0][2] * inv[2][0];
-  double nrm = 1.0;
+  double nrm[3];
   for (int col = 0; col < 3; ++col)
-    nrm *= std::sqrt(M[0][col] * M[0][col] + M[1][col] * M[1][col] + M[2][col] * M[2][col]);
-  if (!(std::fabs(det) > 1e-6 * nrm)) return true;
+    nrm[col] = std::sqrt(M[0][col] * M[0][col] + M[1][col] * M[1][col] + M[2][col] * M[2][col]);
+  if (!(std::fabs(det) > 1e-6 * nrm[0] * nrm[1] * nrm[2])) return true;
   const double side = std::ldexp(1.0, kFix - c.level);
   const int32_t cc[3] = {c.ix, c.iy, c.iz};
-  double amin = INFINITY, amax = -INFINITY, bmin = INFINITY, bmax = -INFINITY;
+  double s[8][3];
   for (int corner = 0; corner < 8; ++corner) {
     double d[3];
     for (int k = 0; k < 3; ++k) d[k] = (cc[k] + ((corner >> k) & 1)) * side - (double)cam.O[k];
-    double s[3];
-    for (int q = 0; q < 3; ++q) s[q] = (inv[q][0] * d[0] + inv[q][1] * d[1] + inv[q][2] * d[2]) / det;
-    double a, b;
-    if (cam.kind == 0) {
-      if (!(s[0] > 0.0)) return true;  // a corner at or behind the eye
-      a = s[1] / s[0];
-      b = s[2] / s[0];
-    } else {
-      a = s[0];
-      b = s[1];
-    }
-    if (!std::isfinite(a) || !std::isfinite(b)) return true;
+    for (int q = 0; q < 3; ++q) s[corner][q] = (inv[q][0] * d[0] + inv[q][1] * d[1] + inv[q][2] * d[2]) / det;
+  }
+  double amin = INFINITY, amax = -INFINITY, bmin = INFINITY, bmax = -INFINITY;
+  auto take = [&](double a, double b) {
     amin = std::min(amin, a);
     amax = std::max(amax, a);
     bmin = std::min(bmin, b);
     bmax = std::max(bmax, b);
+  };
+  if (cam.kind == 0) {
+    double d2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      const double lo = cc[k] * side, hi = lo + side, o = (double)cam.O[k];
+      const double g = o < lo ? lo - o : (o > hi ? o - hi : 0.0);
+      d2 += g * g;
+    }
+    if (!(d2 > 0.0)) return true;  // the eye in the cube or on its surface
+    const double dmax = nrm[0] + W * nrm[1] + H * nrm[2];
+    const double tmin = 0.5 * std::sqrt(d2) / dmax;
+    int nv = 0;
+    for (int corner = 0; corner < 8; ++corner) {
+      if (s[corner][0] >= tmin) {
+        take(s[corner][1] / s[corner][0], s[corner][2] / s[corner][0]);
+        ++nv;
+      }
+      for (int k = 0; k < 3; ++k) {  // the edge to the corner one step up along axis k
+        const int other = corner | (1 << k);
+        if (other == corner) continue;
+        const double t0 = s[corner][0], t1 = s[other][0];
+        if ((t0 < tmin) == (t1 < tmin)) continue;
+        const double lam = (tmin - t0) / (t1 - t0);
+        take((s[corner][1] + lam * (s[other][1] - s[corner][1])) / tmin,
+             (s[corner][2] + lam * (s[other][2] - s[corner][2])) / tmin);
+        ++nv;
+      }
+    }
+    if (nv == 0) return false;  // the cube lies wholly before t_min: behind the eye
+  } else {
+    for (int corner = 0; corner < 8; ++corner) take(s[corner][0], s[corner][1]);
   }
+  if (!std::isfinite(amin) || !std::isfinite(amax) || !std::isfinite(bmin) || !std::isfinite(bmax)) return true;
   // a = 2i + 1 - W, so i = (a + W - 1) / 2
   const double i0 = std::floor((amin + W - 1) * 0.5) - 1.0, i1 = std::ceil((amax + W - 1) * 0.5) + 1.0;
   const double j0 = std::floor((bmin + H - 1) * 0.5) - 1.0, j1 = std::ceil((bmax + H - 1) * 0.5) + 1.0;
@@ -228,12 +266,16 @@ __global__ __launch_bounds__(64) void k_stream_chunk(StreamArgs a) {
   *A = Q;
 }
 
+// Plane B (the chunks of the second compute stream) merged into plane A,
+// then the pixel's value.
 template <int OP>
 __global__ __launch_bounds__(256) void k_stream_finish(const Partial* acc, float* out, float* aux, int64_t n) {
   const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (p >= n) return;
+  Partial A = acc[p];
+  partial_merge<OP>(A, acc[n + p]);
   float o = 0.0f, x = 0.0f;
-  partial_finish<OP>(acc[p], o, x);
+  partial_finish<OP>(A, o, x);
   out[p] = o;
   if (OP == kOpWMean && aux) aux[p] = x;
 }
@@ -253,6 +295,8 @@ amr_status amr_stream_plan_create(const amr_tree* t, const amr_stream_opts* opts
   if (!t->info.host_only) return fail(AMR_EINVAL, "a stream plan is built from a host_only tree");
   if (opts->max_chunk_cells < 1 || opts->max_chunk_cells >= (int64_t(1) << 31))
     return fail(AMR_EINVAL, "max_chunk_cells must be in 1..2^31-1");
+  if (opts->nbuffers != 0 && (opts->nbuffers < 2 || opts->nbuffers > kMaxBuffers))
+    return fail(AMR_EINVAL, "nbuffers must be 0 or 2..8");
   const TreeView& V = t->view;
   const int64_t ncells = V.ncells;
   const int nf = V.nfields;
@@ -266,6 +310,7 @@ amr_status amr_stream_plan_create(const amr_tree* t, const amr_stream_opts* opts
   p->nfields = nf;
   p->host_only = opts->host_only ? 1 : 0;
   p->cap = opts->max_chunk_cells;
+  p->nslots = opts->nbuffers ? opts->nbuffers : 4;
   int64_t off[kMaxLevel + 2];
   for (int l = 0; l <= kMaxLevel + 1; ++l) off[l] = t->info.level_offset[l];
 
@@ -396,9 +441,12 @@ amr_status amr_stream_plan_create(const amr_tree* t, const amr_stream_opts* opts
     p->off_val = p->off_packed + (nf >= 4 ? align_up(p->cap * (int64_t)sizeof(Cell4)) : 0);
     p->slot_bytes = p->off_val + align_up(p->cap * nf * (int64_t)sizeof(float));
     hipError_t e = hipSuccess;
-    for (int s = 0; s < 2 && e == hipSuccess; ++s) e = hipMalloc((void**)&p->slot[s], (size_t)p->slot_bytes);
+    for (int s = 0; s < p->nslots && e == hipSuccess; ++s) e = hipMalloc((void**)&p->slot[s], (size_t)p->slot_bytes);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->copy, hipStreamNonBlocking);
-    for (int s = 0; s < 2 && e == hipSuccess; ++s) {
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->compute2, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->started, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->finished2, hipEventDisableTiming);
+    for (int s = 0; s < p->nslots && e == hipSuccess; ++s) {
       e = hipEventCreateWithFlags(&p->copied[s], hipEventDisableTiming);
       if (e == hipSuccess) e = hipEventCreateWithFlags(&p->consumed[s], hipEventDisableTiming);
     }
@@ -415,7 +463,8 @@ void amr_stream_plan_free(amr_stream_plan* p) {
   if (!p) return;
   if (!p->host_only) {
     (void)hipStreamSynchronize(p->copy);
-    for (int s = 0; s < 2; ++s)
+    (void)hipStreamSynchronize(p->compute2);
+    for (int s = 0; s < p->nslots; ++s)
       if (p->used[s]) (void)hipEventSynchronize(p->consumed[s]);
   }
   release(p);
@@ -431,7 +480,8 @@ amr_status amr_stream_plan_info(const amr_stream_plan* p, amr_stream_plan_info_t
   for (const Chunk& c : p->chunks) out->largest_chunk = std::max(out->largest_chunk, c.ncells);
   out->cells = p->total;
   out->host_bytes = p->total * (int64_t)(sizeof(ChildVal) + 4 * p->nfields + (p->packed ? sizeof(Cell4) : 0));
-  out->device_bytes = 2 * p->slot_bytes;
+  out->device_bytes = p->nslots * p->slot_bytes;
+  out->nbuffers = p->nslots;
   return AMR_OK;
 }
 
@@ -470,7 +520,7 @@ amr_status amr_stream_chunk_rect(const amr_stream_plan* p, int32_t i, const amr_
 
 int64_t amr_stream_workspace_bytes(int32_t W, int32_t H) {
   if (W < 1 || H < 1) return 0;
-  return (int64_t)W * H * (int64_t)sizeof(Partial);
+  return 2 * (int64_t)W * H * (int64_t)sizeof(Partial);
 }
 
 amr_status amr_render_streamed(amr_stream_plan* p, const amr_camera* cam, amr_op op, const amr_render_opts* opts,
@@ -507,10 +557,14 @@ amr_status amr_render_streamed(amr_stream_plan* p, const amr_camera* cam, amr_op
     if (los) need[o.field + 1] = need[o.field + 2] = true;
   }
   const int opi = (int)op;
-  const int64_t nb = (npix + 255) / 256;
-  if (opi == kOpSum) hipLaunchKernelGGL(k_stream_init<kOpSum>, dim3((unsigned)nb), dim3(256), 0, hs, acc, npix);
-  else if (opi == kOpMax) hipLaunchKernelGGL(k_stream_init<kOpMax>, dim3((unsigned)nb), dim3(256), 0, hs, acc, npix);
-  else hipLaunchKernelGGL(k_stream_init<kOpWMean>, dim3((unsigned)nb), dim3(256), 0, hs, acc, npix);
+  const int64_t nb = (npix + 255) / 256, nb2 = (2 * npix + 255) / 256;
+  if (opi == kOpSum) hipLaunchKernelGGL(k_stream_init<kOpSum>, dim3((unsigned)nb2), dim3(256), 0, hs, acc, 2 * npix);
+  else if (opi == kOpMax) hipLaunchKernelGGL(k_stream_init<kOpMax>, dim3((unsigned)nb2), dim3(256), 0, hs, acc, 2 * npix);
+  else hipLaunchKernelGGL(k_stream_init<kOpWMean>, dim3((unsigned)nb2), dim3(256), 0, hs, acc, 2 * npix);
+  // the second compute stream starts after the planes are set
+  hipError_t e0 = hipEventRecord(p->started, hs);
+  if (e0 == hipSuccess) e0 = hipStreamWaitEvent(p->compute2, p->started, 0);
+  if (e0 != hipSuccess) return fail(AMR_EHIP, std::string("streamed render failed: ") + hipGetErrorString(e0));
   const int ml = std::min(cam->max_level, p->lmax);
   int64_t bytes = 0, pixels = 0;
   int32_t launched = 0;
@@ -519,7 +573,11 @@ amr_status amr_render_streamed(amr_stream_plan* p, const amr_camera* cam, amr_op
     const Chunk& c = p->chunks[k];
     int32_t r[4];
     if (!chunk_rect(*cam, c, r)) continue;
-    const int slot = launched & 1;
+    const int slot = launched % p->nslots;
+    // chunks alternate between the caller's stream (plane A) and the plan's
+    // second compute stream (plane B), so one chunk's last rays overlap the
+    // next chunk's walk; the assignment depends on the chunk order only
+    hipStream_t ks = (launched & 1) ? p->compute2 : hs;
     char* buf = p->slot[slot];
     // cells at levels down to the camera's maximum level: a prefix of the chunk
     const int64_t m = c.level_start[ml + 1];
@@ -539,7 +597,7 @@ amr_status amr_render_streamed(amr_stream_plan* p, const amr_camera* cam, amr_op
       bytes += m * 4;
     }
     if (e == hipSuccess) e = hipEventRecord(p->copied[slot], p->copy);
-    if (e == hipSuccess) e = hipStreamWaitEvent(hs, p->copied[slot], 0);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ks, p->copied[slot], 0);
     if (e != hipSuccess) break;
     StreamArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -566,18 +624,20 @@ amr_status amr_render_streamed(amr_stream_plan* p, const amr_camera* cam, amr_op
     a.rw = r[2] - r[0] + 1;
     a.rh = r[3] - r[1] + 1;
     a.px = (a.rw + 7) / 8;
-    a.acc = acc;
+    a.acc = acc + ((launched & 1) ? npix : 0);
     const int blocks = a.px * ((a.rh + 7) / 8);
     const bool sw = std_walk(opi, T, o.field, o.weight_field, los, cam->max_level);
-    if (opi == kOpSum) sw ? launch_chunk<kOpSum, true>(a, blocks, hs) : launch_chunk<kOpSum, false>(a, blocks, hs);
-    else if (opi == kOpMax) sw ? launch_chunk<kOpMax, true>(a, blocks, hs) : launch_chunk<kOpMax, false>(a, blocks, hs);
-    else sw ? launch_chunk<kOpWMean, true>(a, blocks, hs) : launch_chunk<kOpWMean, false>(a, blocks, hs);
+    if (opi == kOpSum) sw ? launch_chunk<kOpSum, true>(a, blocks, ks) : launch_chunk<kOpSum, false>(a, blocks, ks);
+    else if (opi == kOpMax) sw ? launch_chunk<kOpMax, true>(a, blocks, ks) : launch_chunk<kOpMax, false>(a, blocks, ks);
+    else sw ? launch_chunk<kOpWMean, true>(a, blocks, ks) : launch_chunk<kOpWMean, false>(a, blocks, ks);
     e = hipGetLastError();
-    if (e == hipSuccess) e = hipEventRecord(p->consumed[slot], hs);
+    if (e == hipSuccess) e = hipEventRecord(p->consumed[slot], ks);
     p->used[slot] = true;
     pixels += (int64_t)a.rw * a.rh;
     ++launched;
   }
+  if (e == hipSuccess) e = hipEventRecord(p->finished2, p->compute2);
+  if (e == hipSuccess) e = hipStreamWaitEvent(hs, p->finished2, 0);
   if (e == hipSuccess) {
     if (opi == kOpSum) hipLaunchKernelGGL(k_stream_finish<kOpSum>, dim3((unsigned)nb), dim3(256), 0, hs, acc, out, aux, npix);
     else if (opi == kOpMax) hipLaunchKernelGGL(k_stream_finish<kOpMax>, dim3((unsigned)nb), dim3(256), 0, hs, acc, out, aux, npix);
