@@ -473,8 +473,9 @@ def leg_deepzoom(args, ctr, stream):
     res["slice_core0_level22"] = {"points": f"{SZ}x{SZ}", "ms": round(ts * 1e3, 4), "Gpoints_per_s": SZ * SZ / ts / 1e9,
                                   "roofline": roofline("k_slice", SZ * SZ, ts, 12.0 * SZ * SZ, 0.0, ctr)}
     log(f"deep zoom slice: {ts * 1e3:.3f} ms")
+    simgs = None
     if not args.no_stream:
-        res["streamed"] = leg_streamed(args, stream, leaves, cam, out)
+        res["streamed"], simgs = leg_streamed(args, stream, leaves, cam, out)
     if not args.no_oracle:
         torch.cuda.synchronize()
         import oracle
@@ -484,6 +485,8 @@ def leg_deepzoom(args, ctr, stream):
         tree.close()
         ot = oracle.Tree(leaves)
         res["oracle_error"] = oracle_errors(ot, [desc], imgs, ("sum", "max"))
+        if simgs:
+            res["streamed"]["oracle_error"] = oracle_errors(ot, [desc], simgs, ("sum", "max"))
         pts = sample_rays(SZ * SZ, 0.01, 4)
         ref = ot.slice(ot.camera(sd), rays=pts)
         res["slice_core0_level22"]["oracle_mismatches"] = int(np.sum(slv[pts].view(np.int32) != ref.view(np.int32)))
@@ -534,6 +537,7 @@ def leg_streamed(args, stream, leaves, cam, incore):
     ws = torch.empty(amr.StreamPlan.workspace_bytes(cam.W, cam.H) // 4, dtype=torch.float32, device="cuda")
     so = torch.empty(n, dtype=torch.float32, device="cuda")
     peak = h2d_copy_rate(stream)
+    imgs = {}
     res = {"what": "the deep-zoom image rendered from the tree in pinned host memory, chunks (complete subtrees "
                    "under cubes of levels %d-%d, at most %d cells each) copied through %d device buffers while "
                    "earlier chunks render on two compute streams; the timed region includes every "
@@ -548,6 +552,7 @@ def leg_streamed(args, stream, leaves, cam, incore):
         avg = sum(durs) / len(durs)
         ch, by, px = stats[-1]
         got = so.cpu().numpy()
+        imgs[(0, op)] = (got,)
         ref = incore[op].cpu().numpy()
         e = {"avg_ms": round(avg * 1e3, 3), "mrays": n / avg / 1e6, "chunks_walked": ch, "h2d_bytes": by,
              "h2d_GBs": by / avg / 1e9, "pcie_frac": by / avg / 1e9 / PCIE_PEAK_GBS,
@@ -561,7 +566,7 @@ def leg_streamed(args, stream, leaves, cam, incore):
         log(f"streamed {op}: {avg * 1e3:.2f} ms, {ch} chunks, {by / 1e9:.2f} GB at {by / avg / 1e9:.1f} GB/s "
             f"(plain copy {peak:.1f} GB/s)")
     plan.close()
-    return res
+    return res, imgs
 
 
 # ------------------------------------------------------------------ batched
