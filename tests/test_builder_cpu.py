@@ -209,3 +209,44 @@ def test_render_rejects_bad_arguments_without_gpu():
     with pytest.raises(amr.AmrError) as e:  # host-only trees cannot be rendered
         amr.render(T, cam, amr.SUM, out, stream=0)
     assert e.value.status == _abi.AMR_EINVAL
+
+
+def _bad_records(cam):
+    """Hand-made records outside the integer ranges the kernels rely on, each
+    with what it breaks."""
+    import copy
+
+    def mod(**kw):
+        c = copy.deepcopy(cam)
+        for k, v in kw.items():
+            if isinstance(v, tuple):
+                getattr(c, k)[v[0]] = v[1]
+            else:
+                setattr(c, k, v)
+        return c
+
+    return [("image width 0", mod(W=0)), ("image height 32769", mod(H=32769)),
+            ("max_level 25", mod(max_level=25)), ("max_level -1", mod(max_level=-1)), ("kind 2", mod(kind=2)),
+            ("origin beyond 2^30", mod(O=(0, 1 << 30))), ("origin below -2^30", mod(O=(1, -(1 << 30) - 1))),
+            ("direction at 2^30", mod(F=(2, 1 << 30))),
+            ("pixel span beyond 2^30", mod(U=(0, 1 << 25))),
+            ("zero orthographic direction", mod(F=(0, 0)) if cam.kind == 1 else mod(kind=1, F=(0, 0)))]
+
+
+def test_every_out_of_range_record_is_rejected_without_gpu():
+    """The camera checks shared by every entry point that walks rays (here
+    reached through a host-only stream plan, which needs no GPU): each
+    out-of-range record is refused with AMR_EINVAL before any launch."""
+    T = amr.Tree(amrgen.blobs(0), host_only=True)
+    P = amr.StreamPlan(T, T.ncells, host_only=True)
+    for kind in ("ortho", "persp"):
+        d = amrgen.tiny_camera() if kind == "ortho" else amrgen.camera(
+            "persp", (0.5, 0.5, 2.0), (0.5, 0.5, 0.5), (0, 1, 0), 64, 48, fov_y=0.6, max_level=6)
+        cam = amr.set_camera(d, T)
+        assert P.rect(0, cam)[2] >= 0
+        for what, bad in _bad_records(cam):
+            if what == "zero orthographic direction":
+                bad.F[1] = bad.F[2] = 0
+            with pytest.raises(amr.AmrError) as e:
+                P.rect(0, bad)
+            assert e.value.status == _abi.AMR_EINVAL, what

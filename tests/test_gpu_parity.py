@@ -307,6 +307,62 @@ def test_gpu_rejects_bad_arguments():
         assert e.value.status == 1
 
 
+def test_gpu_every_entry_point_rejects_out_of_range_records():
+    """Every entry point that walks rays refuses a record outside the integer
+    ranges the kernels rely on (AMR_EINVAL, nothing launched): the plain,
+    batched, learned-LOD (both forms), streamed, resolution, slice and debug
+    calls."""
+    import paper_1210_8014_amd as amr
+    from paper_1210_8014_amd import lod
+    from tests.test_builder_cpu import _bad_records
+
+    L = amrgen.scene("tiny")
+    R = _R(L)
+    H = amr.Tree(L, host_only=True)
+    P = amr.StreamPlan(H, H.ncells)
+    m = lod.LodModel()
+    n = 1 << 16
+    out = torch.empty(n, device="cuda")
+    aux = torch.empty(n, device="cuda")
+    ws = torch.empty(lod.workspace_bytes(256, 256), dtype=torch.uint8, device="cuda")
+    sws = torch.empty(amr.StreamPlan.workspace_bytes(256, 256) // 4, device="cuda")
+    st = torch.zeros(8, dtype=torch.int64, device="cuda")
+    feat = torch.empty(lod.tiles(256, 256) * 32, dtype=torch.int16, device="cuda")
+    tot = torch.zeros(1, dtype=torch.int64, device="cuda")
+    bits = torch.zeros(R.T.ncells // 32 + 1, dtype=torch.int32, device="cuda")
+    rays = torch.arange(4, dtype=torch.int64, device="cuda")
+    cnt = torch.zeros(4, dtype=torch.int32, device="cuda")
+    offs = torch.zeros(5, dtype=torch.int64, device="cuda")
+    cells = torch.zeros(64, dtype=torch.int32, device="cuda")
+    calls = {
+        "render": lambda c: amr.render(R.T, c, amr.SUM, out),
+        "batch": lambda c: amr.Batch([R.T], [c], [(0, 0)], amr.SUM, [out]),
+        "lod features": lambda c: lod.features(R.T, c, feat, coarse_level=4),
+        "lod render": lambda c: lod.render_lod(R.T, c, amr.SUM, m, out, ws, st),
+        "lod render noalloc": lambda c: lod.render_lod_noalloc(R.T, c, amr.SUM, m, out, st),
+        "streamed": lambda c: P.render(c, amr.SUM, out, sws),
+        "resolution": lambda c: amr.resolution(R.T, c, out),
+        "slice": lambda c: amr.slice_map(R.T, c, out),
+        "count segments": lambda c: amr.count_segments(R.T, c, tot),
+        "mark cells": lambda c: amr.mark_cells(R.T, c, bits, tot),
+        "count rays": lambda c: amr.count_rays(R.T, c, rays, cnt),
+        "trace rays": lambda c: amr.trace_rays(R.T, c, rays, offs, cells),
+    }
+    for kind in ("ortho", "persp"):
+        d = amrgen.tiny_camera() if kind == "ortho" else amrgen.camera(
+            "persp", (0.5, 0.5, 2.0), (0.5, 0.5, 0.5), (0, 1, 0), 256, 256, fov_y=0.6, max_level=6)
+        cam = R.camera(d)
+        for what, bad in _bad_records(cam):
+            if what == "zero orthographic direction":
+                bad.F[1] = bad.F[2] = 0
+            for name, f in calls.items():
+                with pytest.raises(amr.AmrError) as e:
+                    f(bad)
+                assert e.value.status == 1, (kind, what, name)
+    torch.cuda.synchronize()
+    P.close()
+
+
 def test_gpu_distinct_cells_match_oracle():
     """amr_mark_cells: the distinct cells met by all rays of an image (the
     basis of the compulsory traffic) equal the set of cells in the oracle's
