@@ -53,7 +53,7 @@ B_SEG = {"sum": 8, "max": 8, "wmean": 20}  # value(s) + own first-child word per
 B_PIX = {"sum": 4, "max": 4, "wmean": 8}   # output plane(s) per ray
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_disk.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1210_8014_amd", "csrc", f)
-                  for f in ("render.hip", "batch.hip", "traverse.h")]
+                  for f in ("render.hip", "batch.hip", "lod.hip", "post.hip", "stream.hip", "traverse.h", "internal.h")]
 
 
 def log(*a):
@@ -390,6 +390,37 @@ def leg_post(args, tree, cams, descs, sums, stream, ot, leaves, ctr, kappa: floa
         out["blur"]["hbm_frac"] = tb / t_blur / 1e9 / HBM_PEAK_GBS
     out["blur"]["resolution_roofline"] = roofline("k_resolution", npix, t_res, npix * 4.0, 0.0, ctr)
     log(f"blur: resolution {t_res * 1e3:.3f} ms, blur {t_blur * 1e3:.3f} ms per 2048^2 image")
+    # the whole filtered-image pipeline per image: the sum render and its
+    # resolution plane as two walks (single-image default render, then the
+    # resolution walk) or as one walk (amr_render_with_resolution), then the blur
+    img = [torch.empty(npix, device="cuda") for _ in cams]
+
+    def two_walks():
+        for k, c in enumerate(cams):
+            amr.render(tree, c, amr.SUM, img[k])
+            amr.resolution(tree, c, res[k])
+            amr.blur_adaptive(img[k], res[k], W, H, kappa, blurred[k], ws)
+
+    def one_walk():
+        for k, c in enumerate(cams):
+            amr.render_with_resolution(tree, c, amr.SUM, img[k], res[k])
+            amr.blur_adaptive(img[k], res[k], W, H, kappa, blurred[k], ws)
+
+    def fused_only():
+        for k, c in enumerate(cams):
+            amr.render_with_resolution(tree, c, amr.SUM, img[k], res[k])
+
+    for f in (two_walks, one_walk, fused_only):
+        f()
+    t2 = sum(timed_events(two_walks, reps, stream)) / reps / len(cams)
+    t1 = sum(timed_events(one_walk, reps, stream)) / reps / len(cams)
+    tf = sum(timed_events(fused_only, reps, stream)) / reps / len(cams)
+    out["blur"]["pipeline"] = {
+        "what": "sum render + resolution plane + blur of each 2048^2 headline image",
+        "two_walks_ms_per_image": round(t2 * 1e3, 4), "one_walk_ms_per_image": round(t1 * 1e3, 4),
+        "render_with_resolution_ms_per_image": round(tf * 1e3, 4), "speedup": t2 / t1}
+    log(f"filtered image: {t2 * 1e3:.3f} ms with two walks, {t1 * 1e3:.3f} ms with one "
+        f"(render + resolution in one walk {tf * 1e3:.3f} ms)")
     if not args.no_oracle:
         worst = [blur_oracle_errors(ot(leaves), descs[k], blurred[k].cpu().numpy(), kappa) for k in range(len(cams))]
         out["blur"]["oracle_error"] = {"rel": max(w[0] for w in worst), "over_bound": max(w[1] for w in worst),

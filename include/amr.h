@@ -273,6 +273,15 @@ amr_status amr_set_default_variant(amr_tree* t, amr_op op, int32_t v);
  * Sums fp32 Kahan-compensated. */
 amr_status amr_render_resolution(const amr_tree* t, const amr_camera* cam, float* res, amr_stream s);
 
+/* One walk per ray for both an image and its resolution plane: out / aux as
+ * amr_render with the unsplit variant p8x8_w1_fast (bit for bit; same op,
+ * field, weight_field and los_velocity; opts.variant is ignored) and res as
+ * amr_render_resolution (bit for bit), for the cost of one walk with a
+ * slightly heavier visitor instead of two walks.  Same arguments and errors
+ * as those two calls; res: device fp32 H x W. */
+amr_status amr_render_with_resolution(const amr_tree* t, const amr_camera* cam, amr_op op, const amr_render_opts* opts,
+                                      float* out, float* aux, float* res, amr_stream s);
+
 /* Adaptive Gaussian blur (Sec. 2.2) of an image img (device fp32 H x W,
  * row-major) with standard deviation sigma = kappa * res (pixels) at each
  * output pixel, res a resolution plane as above.  The filter is a ladder of

@@ -193,6 +193,16 @@ def resolution(tree: Tree, cam: Camera, res, stream=None):
     return res
 
 
+def render_with_resolution(tree: Tree, cam: Camera, op: int, out, res, aux=None, field: int = 0, weight: int = 0,
+                           los: bool = False, stream=None):
+    """One walk for the image (``out``, as variant p8x8_w1_fast) and its
+    resolution plane (``res``): amr_render_with_resolution."""
+    o = RenderOpts(field, weight, int(bool(los)), -1)
+    _check(lib().amr_render_with_resolution(tree.handle, ctypes.byref(cam), op, ctypes.byref(o), _ptr(out), _ptr(aux),
+                                            _ptr(res), _stream(stream)))
+    return out, res
+
+
 def blur_workspace_bytes(W: int, H: int) -> int:
     return int(lib().amr_blur_workspace_bytes(W, H))
 

@@ -80,6 +80,8 @@ SIGNATURES = {
     "amr_count_rays": (_i32, [_vp, ctypes.POINTER(Camera), _vp, _i64, _vp, _vp]),
     "amr_mark_cells": (_i32, [_vp, ctypes.POINTER(Camera), _vp, _vp, _vp]),
     "amr_render_resolution": (_i32, [_vp, ctypes.POINTER(Camera), _vp, _vp]),
+    "amr_render_with_resolution": (_i32, [_vp, ctypes.POINTER(Camera), _i32, ctypes.POINTER(RenderOpts), _vp, _vp, _vp,
+                                          _vp]),
     "amr_blur_workspace_bytes": (_i64, [_i32, _i32]),
     "amr_blur_adaptive": (_i32, [_vp, _vp, _i32, _i32, ctypes.c_float, _vp, _vp, _i64, _vp]),
     "amr_slice": (_i32, [_vp, ctypes.POINTER(Camera), _i32, _vp, _vp]),

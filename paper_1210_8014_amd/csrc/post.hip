@@ -55,10 +55,67 @@ __global__ __launch_bounds__(64) void k_resolution(TreeView T, CameraView C, flo
     ResVis v;
     v.persp = C.kind == 0;
     walk_fast<ResVis, true>(T, R, E, C.max_level, v);
-    const float L = v.sl - v.cl;
-    if (L > 0.0f) r = (v.sn - v.cn) / L * inv_w0;
+    r = v.res_value(inv_w0);
   }
   res[(int64_t)j * C.W + i] = r;
+}
+
+// One walk per ray for both the projection and the resolution plane: the
+// visitors of the plain unsplit render (p8x8_w1_fast: one wave per 8 x 8
+// packet, whole-ray fast walk) wrapped to also sum the resolution, so that
+// out / aux equal that render's and res equals k_resolution's, bit for bit.
+template <int OP>
+__global__ __launch_bounds__(64) void k_render_res(TreeView T, CameraView C, int field, int wfield, int los,
+                                                  float inv_w0, float* out, float* aux, float* res, int px) {
+  const int lane = threadIdx.x;
+  const int ty = (int)blockIdx.x / px, tx = (int)blockIdx.x - ty * px;
+  const int i = tx * 8 + (lane & 7), j = ty * 8 + (lane >> 3);
+  if (i >= C.W || j >= C.H) return;
+  Ray R;
+  Entry E;
+  const bool hit = setup_ray(C, i, j, R, E);
+  const int64_t nc = T.ncells;
+  const int64_t p = (int64_t)j * C.W + i;
+  float o, r;
+  if (OP == kOpSum) {
+    WithRes<SumVis> v;
+    v.v = T.val + (int64_t)field * nc;
+    v.field0 = field == 0;
+    v.persp = C.kind == 0;
+    if (hit) walk_fast<WithRes<SumVis>, true>(T, R, E, C.max_level, v);
+    o = v.s - v.c;
+    r = v.res_value(inv_w0);
+  } else if (OP == kOpMax) {
+    WithRes<MaxVis> v;
+    v.v = T.val + (int64_t)field * nc;
+    v.m = -INFINITY;
+    v.field0 = field == 0;
+    v.persp = C.kind == 0;
+    if (hit) walk_fast<WithRes<MaxVis>, true>(T, R, E, C.max_level, v);
+    o = v.m;
+    r = v.res_value(inv_w0);
+  } else {
+    WithRes<WMeanVis> v;
+    v.w = T.val + (int64_t)wfield * nc;
+    v.f0 = T.val + (int64_t)field * nc;
+    v.f1 = los ? v.f0 + nc : v.f0;
+    v.f2 = los ? v.f0 + 2 * nc : v.f0;
+    v.los = los;
+    if (packed_los(T, field, wfield, los)) v.pk = T.packed;
+    v.dh[0] = v.dh[1] = v.dh[2] = 0.0f;
+    v.persp = C.kind == 0;
+    if (hit) {
+      const float n = sqrtf((float)(R.d64[0] * R.d64[0] + R.d64[1] * R.d64[1] + R.d64[2] * R.d64[2]));
+      for (int k = 0; k < 3; ++k) v.dh[k] = (float)R.d64[k] / n;
+      walk_fast<WithRes<WMeanVis>, true>(T, R, E, C.max_level, v);
+    }
+    const float W = v.sw - v.cw, Sf = v.sf - v.cf;
+    o = W > 0.0f ? Sf / W : 0.0f;
+    if (aux) aux[p] = W;
+    r = v.res_value(inv_w0);
+  }
+  out[p] = o;
+  res[p] = r;
 }
 
 // Pass 1: h_k(x, y) = sum_d w_k(d) I(x + d, y) / sum_d w_k(d) over the taps
@@ -191,19 +248,57 @@ using namespace amr;
 
 extern "C" {
 
+// 1 / (pixel spacing at unit ray parameter), from the record's pixel step.
+bool inv_spacing(const amr_camera* cam, float* inv_w0) {
+  double u2 = 0.0;
+  for (int k = 0; k < 3; ++k) u2 += (double)cam->U[k] * (double)cam->U[k];
+  if (!(u2 > 0.0)) return false;
+  *inv_w0 = (float)(1.0 / (2.0 * std::sqrt(u2) * 0x1.0p-28));
+  return true;
+}
+
 amr_status amr_render_resolution(const amr_tree* t, const amr_camera* cam, float* res, amr_stream s) {
   amr_status st = check_render_common(t, cam);
   if (st) return st;
   if (!res || ((uintptr_t)res & 3)) return fail(AMR_EINVAL, "null or misaligned output");
-  double u2 = 0.0;
-  for (int k = 0; k < 3; ++k) u2 += (double)cam->U[k] * (double)cam->U[k];
-  if (!(u2 > 0.0)) return fail(AMR_EINVAL, "zero pixel step");
-  const float inv_w0 = (float)(1.0 / (2.0 * std::sqrt(u2) * 0x1.0p-28));
+  float inv_w0;
+  if (!inv_spacing(cam, &inv_w0)) return fail(AMR_EINVAL, "zero pixel step");
   const int px = (cam->W + 7) / 8, py = (cam->H + 7) / 8;
   hipLaunchKernelGGL(k_resolution, dim3((unsigned)(px * py)), dim3(64), 0, (hipStream_t)s, t->view, camera_view(*cam),
                      inv_w0, res, px);
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? AMR_OK : fail(AMR_EHIP, std::string("resolution launch failed: ") + hipGetErrorString(e));
+}
+
+amr_status amr_render_with_resolution(const amr_tree* t, const amr_camera* cam, amr_op op, const amr_render_opts* opts,
+                                      float* out, float* aux, float* res, amr_stream s) {
+  amr_status st = check_render_common(t, cam);
+  if (st) return st;
+  if (!out || !res) return fail(AMR_EINVAL, "null output");
+  if (((uintptr_t)out & 3) || ((uintptr_t)aux & 3) || ((uintptr_t)res & 3)) return fail(AMR_EINVAL, "misaligned output");
+  if (op != AMR_SUM && op != AMR_MAX && op != AMR_WMEAN) return fail(AMR_EINVAL, "bad op");
+  const amr_render_opts o = opts ? *opts : amr_render_opts{0, 0, 0, -1};
+  const int nf = t->info.nfields;
+  const int los = op == AMR_WMEAN && o.los_velocity ? 1 : 0;
+  if (o.field < 0 || o.field + (los ? 2 : 0) >= nf) return fail(AMR_EINVAL, "field index out of range");
+  if (op == AMR_WMEAN && (o.weight_field < 0 || o.weight_field >= nf)) return fail(AMR_EINVAL, "bad weight field");
+  float inv_w0;
+  if (!inv_spacing(cam, &inv_w0)) return fail(AMR_EINVAL, "zero pixel step");
+  const int px = (cam->W + 7) / 8, py = (cam->H + 7) / 8;
+  const dim3 g((unsigned)(px * py));
+  hipStream_t hs = (hipStream_t)s;
+  const CameraView C = camera_view(*cam);
+  if (op == AMR_SUM)
+    hipLaunchKernelGGL(k_render_res<kOpSum>, g, dim3(64), 0, hs, t->view, C, o.field, o.weight_field, los, inv_w0,
+                       out, aux, res, px);
+  else if (op == AMR_MAX)
+    hipLaunchKernelGGL(k_render_res<kOpMax>, g, dim3(64), 0, hs, t->view, C, o.field, o.weight_field, los, inv_w0,
+                       out, aux, res, px);
+  else
+    hipLaunchKernelGGL(k_render_res<kOpWMean>, g, dim3(64), 0, hs, t->view, C, o.field, o.weight_field, los, inv_w0,
+                       out, aux, res, px);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? AMR_OK : fail(AMR_EHIP, std::string("render launch failed: ") + hipGetErrorString(e));
 }
 
 int64_t amr_blur_workspace_bytes(int32_t W, int32_t H) {

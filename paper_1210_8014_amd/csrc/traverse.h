@@ -811,27 +811,51 @@ struct TraceVis {
 // so each cell's side is divided by the parameter at the middle of its
 // chord, (en/da + nb/db) / 2; the caller divides the result by the spacing
 // at unit parameter (orthographic: the constant spacing).
-struct ResVis {
-  static constexpr bool kNeedsLength = true;
-  static constexpr bool kNeedsParams = true;
+struct ResAcc {
   int persp = 1;
   float tm = 1.0f;
   float sn = 0.0f, cn = 0.0f, sl = 0.0f, cl = 0.0f;  // Kahan pairs: sum(len side / t), sum(len)
-  AMR_HD void fetch(int32_t) {}
-  AMR_HD void fetch0(int32_t, float) {}
-  AMR_HD void params(int32_t en, float inv_da, int32_t nb, float inv_db) {
+  AMR_HD void res_params(int32_t en, float inv_da, int32_t nb, float inv_db) {
     if (persp) tm = 0.5f * ((float)en * inv_da + (float)nb * inv_db);
   }
-  AMR_HD void seg(int32_t, int lvl, float len, int32_t, int32_t, int32_t) {
+  AMR_HD void res_seg(int lvl, float len) {
     const float side = ldexpf(1.0f, -lvl);  // exact
     kahan_add(sn, cn, len * side * rcp(tm));
     kahan_add(sl, cl, len);
+  }
+  // resolution in units of the spacing at unit parameter; 0 without length
+  AMR_HD float res_value(float inv_w0) const {
+    const float L = sl - cl;
+    return L > 0.0f ? (sn - cn) / L * inv_w0 : 0.0f;
   }
 #if defined(__HIP_DEVICE_COMPILE__)
   __device__ static float rcp(float x) { return __builtin_amdgcn_rcpf(x); }  // 1 ulp
 #else
   static float rcp(float x) { return 1.0f / x; }
 #endif
+};
+
+struct ResVis : ResAcc {
+  static constexpr bool kNeedsLength = true;
+  static constexpr bool kNeedsParams = true;
+  AMR_HD void fetch(int32_t) {}
+  AMR_HD void fetch0(int32_t, float) {}
+  AMR_HD void params(int32_t en, float inv_da, int32_t nb, float inv_db) { res_params(en, inv_da, nb, inv_db); }
+  AMR_HD void seg(int32_t, int lvl, float len, int32_t, int32_t, int32_t) { res_seg(lvl, len); }
+};
+
+// A projection's visitor V that also accumulates the local resolution, so
+// that one walk yields the image and its resolution plane: V sees exactly
+// what it sees alone, and the resolution sums exactly what ResVis sums.
+template <class V>
+struct WithRes : V, ResAcc {
+  static constexpr bool kNeedsLength = true;
+  static constexpr bool kNeedsParams = true;
+  AMR_HD void params(int32_t en, float inv_da, int32_t nb, float inv_db) { res_params(en, inv_da, nb, inv_db); }
+  AMR_HD void seg(int32_t node, int lvl, float len, int32_t c0, int32_t c1, int32_t c2) {
+    V::seg(node, lvl, len, c0, c1, c2);
+    res_seg(lvl, len);
+  }
 };
 
 // Sets bit `node` of a bitmap for every cell met and counts the bits it

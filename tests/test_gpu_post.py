@@ -184,3 +184,47 @@ def test_gpu_slice_bit_exact():
     with pytest.raises(amr.AmrError) as e:  # perspective records have no plane
         amr.slice_map(T, amr.set_camera(amrgen.disk_camera(10.0, 8, 8), T), torch.empty(64, device="cuda"))
     assert e.value.status == 1
+
+
+def test_gpu_render_with_resolution_equals_the_two_walks():
+    """amr_render_with_resolution: the image bit-identical to amr_render with
+    the unsplit variant p8x8_w1_fast and the plane bit-identical to
+    amr_render_resolution, for every op, on the tiny scene, random trees
+    with degenerate and inside cameras, and the disk at 2048^2 (both already
+    checked against the oracle by the tests of those two calls)."""
+    import paper_1210_8014_amd as amr
+
+    v0 = amr.variants().index("p8x8_w1_fast")
+
+    def same(T, d, what):
+        cam = amr.set_camera(d, T)
+        n = cam.W * cam.H
+        nf = int(T.info.nfields)
+        jobs = [(amr.SUM, {}), (amr.MAX, {})]
+        if nf >= 4:
+            jobs += [(amr.WMEAN, dict(field=1, weight=0, los=True)), (amr.SUM, dict(field=2)),
+                     (amr.WMEAN, dict(field=3, weight=1, los=False))]
+        ref_res = torch.empty(n, device="cuda")
+        amr.resolution(T, cam, ref_res)
+        for op, kw in jobs:
+            a, x = torch.full((n,), -7.0, device="cuda"), torch.full((n,), -7.0, device="cuda")
+            b, y, r = (torch.full((n,), -7.0, device="cuda") for _ in range(3))
+            amr.render(T, cam, op, a, x if op == amr.WMEAN else None, variant=v0, **kw)
+            amr.render_with_resolution(T, cam, op, b, r, y if op == amr.WMEAN else None, **kw)
+            torch.cuda.synchronize()
+            assert torch.equal(a.view(torch.int32), b.view(torch.int32)), (what, op, kw)
+            if op == amr.WMEAN:
+                assert torch.equal(x.view(torch.int32), y.view(torch.int32)), (what, op, kw)
+            assert torch.equal(ref_res.view(torch.int32), r.view(torch.int32)), (what, op, kw)
+
+    L = amrgen.scene("tiny")
+    same(amr.Tree(L), amrgen.tiny_camera(131, 97, max_level=6), "tiny")
+    rng = np.random.default_rng(8)
+    Lr = amrgen.random_tree(78, lmax=5, p_refine=0.45, nfields=4)
+    Lr.fields[1:] -= 5.0
+    T = amr.Tree(Lr)
+    for k, d in enumerate(rand_cams(rng, 4, 23, 17) + degenerate_cams()[:6] + rand_cams(rng, 3, 19, 11, inside=True)):
+        same(T, dict(d, max_level=int(rng.integers(2, 6))), f"random {k}")
+    T = amr.Tree(amrgen.scene("disk"))
+    same(T, amrgen.disk_camera(45.0, 2048, 2048, max_level=16), "disk 2048")
+    T.close()
