@@ -27,10 +27,14 @@ constexpr int kBlurLevels = 11;
 constexpr int kBlurRmax = 48;  // ceil(3 x 16)
 constexpr float kBlurSigma0 = 0.5f;
 constexpr int kRowTile = 256;  // pixels of a row per block of pass 1
+// ceil(3 sigma_k) of the ladder, sigma_k = 0.5 x 2^(k/2) (checked against the
+// computed radii when the ladder is built)
+__constant__ constexpr int kBlurMaxRadius[kBlurLevels] = {2, 3, 3, 5, 6, 9, 12, 17, 24, 34, 48};
 
 struct BlurLadder {
   int32_t R[kBlurLevels];
-  float w[kBlurLevels][kBlurRmax + 1];  // w[k][d] = exp(-d^2 / (2 sigma_k^2)), d = 0..R[k]
+  float w[kBlurLevels][kBlurRmax + 1];  // w[k][d] = exp(-d^2 / (2 sigma_k^2)), d = 0..R[k], 0 beyond
+  double total[kBlurLevels];            // sum of w[k][|d|] over d = -R[k]..R[k]: a window inside the image
 };
 
 BlurLadder make_ladder() {
@@ -39,8 +43,20 @@ BlurLadder make_ladder() {
     const double s = (double)kBlurSigma0 * std::pow(2.0, 0.5 * k);
     L.R[k] = (int32_t)std::ceil(3.0 * s);
     for (int d = 0; d <= kBlurRmax; ++d) L.w[k][d] = d <= L.R[k] ? (float)std::exp(-(double)d * d / (2.0 * s * s)) : 0.f;
+    double tail = 0.0;
+    for (int d = L.R[k]; d >= 1; --d) tail += (double)L.w[k][d];
+    L.total[k] = (double)L.w[k][0] + 2.0 * tail;
   }
   return L;
+}
+
+// Weight of level k's taps at distances 0..R inside [0, n) around position x:
+// the full window less the taps past either end (none away from the borders).
+__device__ inline double window_weight(const BlurLadder& L, int k, int x, int n) {
+  double out = 0.0;
+  for (int d = x + 1; d <= L.R[k]; ++d) out += (double)L.w[k][d];
+  for (int d = n - x; d <= L.R[k]; ++d) out += (double)L.w[k][d];
+  return L.total[k] - out;
 }
 
 __global__ __launch_bounds__(64) void k_resolution(TreeView T, CameraView C, float inv_w0, float* res, int px) {
@@ -119,7 +135,10 @@ __global__ __launch_bounds__(64) void k_render_res(TreeView T, CameraView C, int
 }
 
 // Pass 1: h_k(x, y) = sum_d w_k(d) I(x + d, y) / sum_d w_k(d) over the taps
-// inside the row, for every level k; planes h[k][H][W].
+// inside the row, for every level k; planes h[k][H][W].  Each distance d is
+// visited once: the pair I(x - d) + I(x + d) (zero outside the row, staged
+// in LDS) is added, in fp64, to the sum of every level whose window reaches
+// d; the weights are the same for every thread.
 __global__ __launch_bounds__(kRowTile) void k_blur_rows(const float* __restrict__ img, int W, int H, BlurLadder Lad,
                                                        float* __restrict__ h) {
   __shared__ float row[kRowTile + 2 * kBlurRmax];
@@ -131,18 +150,22 @@ __global__ __launch_bounds__(kRowTile) void k_blur_rows(const float* __restrict_
   __syncthreads();
   const int x = x0 + t;
   if (x >= W) return;
-  const int64_t plane = (int64_t)W * H;
-  for (int k = 0; k < kBlurLevels; ++k) {
-    const int R = Lad.R[k];
-    const int lo = x - R < 0 ? -x : -R, hi = x + R >= W ? W - 1 - x : R;
-    double acc = 0.0, nrm = 0.0;
-    for (int d = lo; d <= hi; ++d) {
-      const double wd = (double)Lad.w[k][d < 0 ? -d : d];
-      acc += wd * (double)row[t + kBlurRmax + d];
-      nrm += wd;
-    }
-    h[k * plane + (int64_t)y * W + x] = (float)(acc / nrm);
+  const float* r = row + t + kBlurRmax;
+  double acc[kBlurLevels];
+  const double c = (double)r[0];
+  AMR_UNROLL
+  for (int k = 0; k < kBlurLevels; ++k) acc[k] = (double)Lad.w[k][0] * c;
+  AMR_UNROLL
+  for (int d = 1; d <= kBlurRmax; ++d) {
+    const double pair = (double)r[-d] + (double)r[d];
+    AMR_UNROLL
+    for (int k = 0; k < kBlurLevels; ++k)
+      if (d <= kBlurMaxRadius[k]) acc[k] += (double)Lad.w[k][d] * pair;
   }
+  const int64_t plane = (int64_t)W * H;
+  AMR_UNROLL
+  for (int k = 0; k < kBlurLevels; ++k)
+    h[k * plane + (int64_t)y * W + x] = (float)(acc[k] / window_weight(Lad, k, x, W));
 }
 
 // Pass 2: per pixel, the column filter of the levels around sigma(p) and
@@ -189,16 +212,16 @@ __global__ __launch_bounds__(256) void k_blur_cols(const float* __restrict__ img
       b[1] = b[0];
       continue;
     }
+    // taps at distances 1..R in pairs, those outside the image left out
     const int R = Lad.R[k];
-    const int d0 = y - R < 0 ? -y : -R, d1 = y + R >= H ? H - 1 - y : R;
     const float* col = h + k * plane + x;
-    double acc = 0.0, nrm = 0.0;
-    for (int d = d0; d <= d1; ++d) {
-      const double wd = (double)Lad.w[k][d < 0 ? -d : d];
-      acc += wd * (double)col[(int64_t)(y + d) * W];
-      nrm += wd;
+    double acc = (double)Lad.w[k][0] * (double)col[(int64_t)y * W];
+    for (int d = 1; d <= R; ++d) {
+      const double up = y - d >= 0 ? (double)col[(int64_t)(y - d) * W] : 0.0;
+      const double dn = y + d < H ? (double)col[(int64_t)(y + d) * W] : 0.0;
+      acc += (double)Lad.w[k][d] * (up + dn);
     }
-    b[q] = acc / nrm;
+    b[q] = acc / window_weight(Lad, k, y, H);
   }
   out[p] = (float)((1.0 - (double)a) * b[0] + (double)a * b[1]);
 }
@@ -316,6 +339,13 @@ amr_status amr_blur_adaptive(const float* img, const float* res, int32_t W, int3
   if (out == img) return fail(AMR_EINVAL, "out must not alias img");
   if (workspace_bytes < amr_blur_workspace_bytes(W, H)) return fail(AMR_ECAPACITY, "workspace too small");
   static const BlurLadder lad = make_ladder();
+  static const bool radii_ok = [] {
+    const int host_radius[kBlurLevels] = {2, 3, 3, 5, 6, 9, 12, 17, 24, 34, 48};
+    for (int k = 0; k < kBlurLevels; ++k)
+      if (lad.R[k] != host_radius[k]) return false;
+    return true;
+  }();
+  if (!radii_ok) return fail(AMR_EINVAL, "blur ladder radii differ from the kernel's table");
   float* h = (float*)workspace;
   hipStream_t hs = (hipStream_t)s;
   hipLaunchKernelGGL(k_blur_rows, dim3((unsigned)((W + kRowTile - 1) / kRowTile), (unsigned)H), dim3(kRowTile), 0, hs,
