@@ -251,7 +251,10 @@ def test_gpu_deepzoom_full_size_sampled():
     """Deep zoom at full size: ~201M leaves to level 22, the eye inside the disk
     2^-9 box from core 0, 4096^2 pixels, automatic maximum level 21, so cells
     at levels 18..21 (FP64 chords) are crossed.  Sum and max on a seeded 1% ray
-    sample for the default and the unsplit walk; cell sequences of 1500 rays."""
+    sample for the default and the unsplit walk; cell sequences of 1500 rays;
+    the streamed render of the same image from the tree in host memory, in
+    the bench's configuration, on the same sample (max also bit-identical to
+    the in-memory render); slices at levels 22, 21 and 18."""
     import paper_1210_8014_amd as amr
 
     log("generating deep-zoom scene")
@@ -262,6 +265,12 @@ def test_gpu_deepzoom_full_size_sampled():
     log("library tree", R.T.ncells, "cells")
     OT = oracle.Tree(L)
     log("oracle tree", OT.nodes, "nodes")
+    # the streamed render as the bench times it: the tree in pinned host
+    # memory, chunks of at most 8M cells through four device buffers
+    H = amr.Tree(L, host_only=True)
+    P = amr.StreamPlan(H, 8 << 20, nbuffers=4)
+    H.close()
+    log("stream plan", P.nchunks, "chunks")
     del L
     camd = amrgen.deepzoom_camera()
     cam = R.camera(camd)
@@ -276,6 +285,22 @@ def test_gpu_deepzoom_full_size_sampled():
         log("  worst sum rel", res["sum"])
     offs, cells = R.trace(cam, rays[::112])
     assert cells[:, 0].max() >= 18
+    ocam = OT.camera(camd)
+    ws = torch.empty(amr.StreamPlan.workspace_bytes(cam.W, cam.H) // 4, device="cuda")
+    so = torch.empty(n, device="cuda")
+    for op in (amr.SUM, amr.MAX):
+        st = P.render(cam, op, so, ws)
+        torch.cuda.synchronize()
+        got = so.cpu().numpy()
+        log("streamed", op, "chunks walked", st[0], "bytes copied", st[1])
+        if op == amr.MAX:
+            ref_in, _ = R.full(cam, op, variant=0)
+            assert np.array_equal(got.view(np.int32), ref_in.view(np.int32)), "streamed max differs from in-memory"
+            parity.check_max(got[rays], OT.render(ocam, oracle.MAX, rays=rays)["max"], "streamed deepzoom max")
+        else:
+            log("  worst sum rel", parity.check_sum(got[rays], OT.render(ocam, oracle.SUM, rays=rays)["val"],
+                                                    "streamed deepzoom sum"))
+    P.close()
     # slice maps through core 0 at the full depth and at the camera's level:
     # a 2048^2 plane 2^-10 box wide (pixel 2^-21 box), every point bit for bit
     import paper_1210_8014_amd as amr
