@@ -547,9 +547,6 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
   int plv = -2;      // level of that parent (-2: none, never equal to jr)
   int jr = -1;       // restart level (>= -1)
   int32_t nseg = 0;
-  // per-axis copies of E.exact (lane masks, not integer bits, so that no
-  // select is spent packing and unpacking them on every cell)
-  bool ex0 = E.exact & 1, ex1 = E.exact & 2, ex2 = E.exact & 4;
   for (;;) {
     int lvl;
     int32_t node;
@@ -583,15 +580,16 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
         // three products would run on every cell)
         int32_t en = E.en;
         AMR_KEEP_HERE(en);
-        // non-exact coordinates are known down to level lam; their lower
-        // bits are left over from earlier cells and cleared here
+        // the coordinates are known down to level lam (their lower bits are
+        // left over from earlier cells and cleared here); the bit of each
+        // axis at this level is decided exactly from the entry parameter,
+        // which for an axis whose stored coordinate is exact (an axis just
+        // crossed) gives that coordinate's own bit
         const int32_t known = ~((int32_t(1) << (kFix - E.lam)) - 1);
-        const bool exk[3] = {ex0, ex1, ex2};
         const int32_t dvk[3] = {dv0, dv1, dv2};
         const int32_t cok[3] = {co0, co1, co2};
         AMR_UNROLL
         for (int k = 0; k < 3; ++k) {
-          if (exk[k]) continue;
           const int32_t M = (E.p[k] & known) + (int32_t(1) << s);
           E.p[k] = mul64(en, dvk[k]) >= mul64(M + cok[k] - 1, E.da) ? M : (E.p[k] & known);
         }
@@ -644,9 +642,6 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
     // the rest of the next cell's entry state, set before the end test so
     // that both ways out of this iteration carry the same values (a ray that
     // ends discards them; on return E is not meaningful)
-    ex0 = t0;
-    ex1 = t1;
-    ex2 = t2;
     E.lam = lvl;
     E.en = nb;
     E.da = db;
