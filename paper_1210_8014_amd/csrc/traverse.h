@@ -544,23 +544,13 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
   uint32_t mb = morton3((uint32_t)(E.p[0] >> sb), (uint32_t)(E.p[1] >> sb), (uint32_t)(E.p[2] >> sb));
   const int32_t offb = T.off[b0];  // first cell of the complete base level
   int32_t pfc = -1;  // first-child index of the current cell's parent (-1: none cached)
-  int plv = -2;      // level of that parent (-2: none, never equal to jr)
-  int jr = -1;       // restart level (>= -1)
+  int plv = -2;      // level of that parent (-2: none)
   int32_t nseg = 0;
+  // where the next cell's descent starts: its level and cell (set at the end
+  // of each step: the base-level cell, or the previous cell's sibling)
+  int lvl = b0;
+  int32_t node = offb + (int32_t)((mb ^ fm) & mask3);
   for (;;) {
-    int lvl;
-    int32_t node;
-    if (jr == plv) {
-      lvl = jr + 1;  // sibling of the previous cell
-      const int s = kFix - lvl;
-      node = pfc + (int32_t)(octant_bits(E.p[0], E.p[1], E.p[2], s) ^ (fm & 7u));
-    } else {
-      // (pfc and plv keep their old values: after a base-level cell jr is
-      // -1 and never matches; after a deeper one, plv is that cell's parent
-      // level, set by the descent or the sibling step that reached it)
-      lvl = b0;
-      node = offb + (int32_t)((mb ^ fm) & mask3);
-    }
     AMR_CHECK_CELL(T, node);
     float v0;
     for (;;) {
@@ -651,11 +641,10 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
     } else {
       if (E.p[0] >= R.stop[0] || E.p[1] >= R.stop[1] || E.p[2] >= R.stop[2]) break;
     }
-    // restart level and base-cell steps
+    // restart level, base-cell steps and where the next descent starts
     if (lvl == b0) {
       // a base-level cell (most cells of a typical tree): every tied axis
-      // moves the base cell, and the next cell restarts at the base level
-      jr = -1;
+      // moves the base cell, and the next cell is found from the base level
       // one increment along the exit axis; an edge or corner (several tied
       // axes, rare) moves along every tied axis
       const uint32_t mk = p2 ? 0x24924924u : (p1 ? 0x12492492u : 0x09249249u);
@@ -666,12 +655,13 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
         mb = morton_inc(mb, 1, t1);
         mb = morton_inc(mb, 2, t2);
       }
+      node = offb + (int32_t)((mb ^ fm) & mask3);
     } else {
       // a tied axis whose new coordinate at this level, c + 1, ends in r
       // zero bits (the old c in r one-bits) carries r levels up
       const int span = lvl - b0;
       const int32_t bmask = (int32_t(1) << span) - 1;
-      jr = lvl - 1;
+      int jr = lvl - 1;
       if (t0) {
         const int32_t c1 = E.p[0] >> s;
         jr = min(jr, lvl - 1 - (int)__builtin_ctz((uint32_t)c1));
@@ -687,7 +677,18 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
         jr = min(jr, lvl - 1 - (int)__builtin_ctz((uint32_t)c1));
         mb = morton_inc(mb, 2, (c1 & bmask) == 0);
       }
+      // the next cell is the sibling of this one when the restart level is
+      // that of the cached parent (plv is this cell's parent level, set by
+      // the descent or the sibling step that reached it); else it is found
+      // from the base level
+      if (jr == plv) {
+        node = pfc + (int32_t)(octant_bits(E.p[0], E.p[1], E.p[2], kFix - 1 - jr) ^ (fm & 7u));
+        lvl = jr + 1;
+        continue;
+      }
+      node = offb + (int32_t)((mb ^ fm) & mask3);
     }
+    lvl = b0;
   }
   return nseg;
 }
