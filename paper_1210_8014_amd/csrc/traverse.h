@@ -543,8 +543,10 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
   const uint32_t fm = (f0 ? 0x09249249u : 0u) | (f1 ? 0x12492492u : 0u) | (f2 ? 0x24924924u : 0u);
   uint32_t mb = morton3((uint32_t)(E.p[0] >> sb), (uint32_t)(E.p[1] >> sb), (uint32_t)(E.p[2] >> sb));
   const int32_t offb = T.off[b0];  // first cell of the complete base level
-  int32_t pfc = -1;  // first-child index of the current cell's parent (-1: none cached)
-  int plv = -2;      // level of that parent (-2: none)
+  // first-child index of the current cell's parent: set by every descent
+  // step and kept by a sibling step, so it is that of the level lvl - 1 for
+  // every cell below the base level
+  int32_t pfc = -1;
   int32_t nseg = 0;
   // where the next cell's descent starts: its level and cell (set at the end
   // of each step: the base-level cell, or the previous cell's sibling)
@@ -562,7 +564,6 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
         break;
       }
       pfc = w;
-      plv = lvl;
       ++lvl;
       const int s = kFix - lvl;
       if (lvl > E.lam) {
@@ -678,10 +679,9 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
         mb = morton_inc(mb, 2, (c1 & bmask) == 0);
       }
       // the next cell is the sibling of this one when the restart level is
-      // that of the cached parent (plv is this cell's parent level, set by
-      // the descent or the sibling step that reached it); else it is found
-      // from the base level
-      if (jr == plv) {
+      // that of the cached parent, lvl - 1; else it is found from the base
+      // level
+      if (jr == lvl - 1) {
         node = pfc + (int32_t)(octant_bits(E.p[0], E.p[1], E.p[2], kFix - 1 - jr) ^ (fm & 7u));
         lvl = jr + 1;
         continue;
