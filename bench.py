@@ -726,6 +726,47 @@ def lod_leg(seed: int = 100):
     return res
 
 
+# ------------------------------------------------------------------ issue-rate probe
+
+def issue_probe(reps: int = 3, blocks: int = 8192, iters: int = 2048) -> dict:
+    """Wave64 instructions per cycle over the chip of single VALU instructions,
+    each on 8 independent register chains per lane with every wave slot filled
+    (libamrprobe.so, csrc/probe.hip): per cycle of the core clock measured in
+    the kernel, and per cycle of the nominal 2.4 GHz."""
+    import ctypes
+
+    from paper_1210_8014_amd import build as amr_build
+
+    if not os.path.exists(amr_build.PROBE_LIB):
+        raise SystemExit(f"{amr_build.PROBE_LIB} is missing: build first")
+    lib = ctypes.CDLL(amr_build.PROBE_LIB)
+    lib.amrprobe_name.restype = ctypes.c_char_p
+    lib.amrprobe_run.argtypes = [ctypes.c_int32] * 4 + [ctypes.POINTER(ctypes.c_float)] * 2
+    waves = blocks * 4
+    out = {}
+    # a few launches first, so that the clock has ramped up before the timed kinds
+    warm_ms = (ctypes.c_float * 8)()
+    warm_mhz = (ctypes.c_float * 8)()
+    if lib.amrprobe_run(0, blocks, iters, 8, warm_ms, warm_mhz) != 0:
+        raise SystemExit("probe warm-up failed")
+    for k in range(lib.amrprobe_kinds()):
+        per_launch = waves * iters * lib.amrprobe_per_iter(k)
+        ms = (ctypes.c_float * reps)()
+        mhz = (ctypes.c_float * reps)()
+        rc = lib.amrprobe_run(k, blocks, iters, reps, ms, mhz)
+        if rc != 0:
+            raise SystemExit(f"probe {k} failed: hip error {rc}")
+        r = min(range(reps), key=lambda i: ms[i])
+        t = ms[r] * 1e-3
+        name = lib.amrprobe_name(k).decode()
+        out[name] = {"per_cycle": round(per_launch / (t * mhz[r] * 1e6), 1),
+                     "per_nominal_cycle": round(per_launch / (t * 2.4e9), 1),
+                     "clock_mhz": round(mhz[r]), "ms": round(t * 1e3, 3)}
+        log(f"{name:36s} {out[name]['per_cycle']:6.1f} per cycle at {mhz[r]:6.0f} MHz "
+            f"({out[name]['per_nominal_cycle']:6.1f} per 2.4 GHz cycle, {t * 1e3:.3f} ms)")
+    return out
+
+
 # ------------------------------------------------------------------ CPU baseline
 
 def cpu_model() -> str:
@@ -789,6 +830,8 @@ def main():
     ap.add_argument("--no-deepzoom", action="store_true", help="skip the deep-zoom leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-image batched leg")
     ap.add_argument("--no-stream", action="store_true", help="skip the streamed (host-resident tree) render")
+    ap.add_argument("--issue-probe", action="store_true",
+                    help="only measure the issue rate of single VALU instructions (libamrprobe.so) and print it")
     ap.add_argument("--only-headline", action="store_true", help="headline step only (profiling runs)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, run one 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
@@ -797,6 +840,11 @@ def main():
         print("bench.py: this build renders on one GPU only; runs on more than one GPU are not supported",
               file=sys.stderr)
         sys.exit(2)
+    if args.issue_probe:
+        rates = issue_probe()
+        print(json.dumps({"metric": "VALU issue rate of single instructions", "unit": "wave64 instructions per cycle "
+                          "over the chip (peak 512)", "rates": rates}), flush=True)
+        return
     if args.only_headline:
         args.no_cpu_baseline = args.no_oracle = args.no_lod = args.no_deepzoom = args.no_batch = True
 

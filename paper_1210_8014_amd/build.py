@@ -11,6 +11,9 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libamr.so")
+# the VALU issue-rate probe (a measurement aid, not part of the library)
+PROBE_SRC = "probe.hip"
+PROBE_LIB = os.path.join(HERE, "libamrprobe.so")
 SOURCES = ["render.hip", "batch.hip", "lod.hip", "post.hip", "stream.hip", "tree.cpp"]
 HEADERS = ["traverse.h", "internal.h", os.path.join("..", "..", "include", "amr.h")]
 
@@ -51,6 +54,12 @@ def build(force: bool = True, verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    tmp = PROBE_LIB + ".tmp"
+    cmd = ["hipcc"] + HIP_FLAGS + ["-shared", os.path.join(CSRC, PROBE_SRC), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, PROBE_LIB)
     return LIB
 
 

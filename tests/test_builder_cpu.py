@@ -34,6 +34,26 @@ def test_library_exports_every_declared_symbol():
     assert set(names) <= declared, set(names) - declared
 
 
+def test_issue_probe_library_exports_its_calls():
+    # the measurement aid built beside the library (not part of the C ABI)
+    from paper_1210_8014_amd import build as amr_build
+
+    if not os.path.exists(amr_build.PROBE_LIB):
+        pytest.skip("libamrprobe.so not built")
+    lib = ctypes.CDLL(amr_build.PROBE_LIB)
+    for n in ("amrprobe_kinds", "amrprobe_name", "amrprobe_per_iter", "amrprobe_run"):
+        assert hasattr(lib, n), n
+    lib.amrprobe_name.restype = ctypes.c_char_p
+    assert lib.amrprobe_kinds() >= 10 and lib.amrprobe_per_iter(0) == 32
+    assert lib.amrprobe_per_iter(lib.amrprobe_kinds()) == 0
+    assert lib.amrprobe_name(0) == b"v_add_u32" and lib.amrprobe_name(-1) == b"invalid"
+    # argument errors are returned before any device call
+    ms = (ctypes.c_float * 1)()
+    lib.amrprobe_run.argtypes = [ctypes.c_int32] * 4 + [ctypes.POINTER(ctypes.c_float)] * 2
+    assert lib.amrprobe_run(lib.amrprobe_kinds(), 1, 1, 1, ms, ms) != 0
+    assert lib.amrprobe_run(0, 0, 1, 1, ms, ms) != 0
+
+
 def _cells_by_level(T):
     child, vals, md = T.host_arrays()
     off = np.array(list(T.info.level_offset))
