@@ -117,7 +117,7 @@ __global__ __launch_bounds__(64) void k_render_res(TreeView T, CameraView C, int
     v.f1 = los ? v.f0 + nc : v.f0;
     v.f2 = los ? v.f0 + 2 * nc : v.f0;
     v.los = los;
-    if (packed_los(T, field, wfield, los)) v.pk = T.packed;
+    if (packed_los(T, field, wfield, los)) v.use_packed(T);
     v.dh[0] = v.dh[1] = v.dh[2] = 0.0f;
     v.persp = C.kind == 0;
     if (hit) {

@@ -70,7 +70,8 @@ __global__ __launch_bounds__(64 * WPB) void k_render(RenderArgs A) {
 // Partial sums meet in LDS and wave 0 merges them in span order.
 // STD: the render may take walk_span's kStd walk (std_walk).
 template <int OP, int K, int REMAP, bool STD = false>
-__global__ __launch_bounds__(64 * K) void k_render_split(RenderArgs A) {
+__global__ __launch_bounds__(64 * K) __attribute__((amdgpu_waves_per_eu(OP == kOpWMean ? 8 : 1))) void k_render_split(
+    RenderArgs A) {
   __shared__ float part[(K - 1) * 4 * 64];
   const int lane = threadIdx.x & 63, w = (int)(threadIdx.x >> 6);
   const int packet =

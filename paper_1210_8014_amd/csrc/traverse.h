@@ -186,6 +186,26 @@ __device__ inline bool amr_mask_here(bool c) {
 inline bool amr_mask_here(bool c) { return c; }
 #endif
 
+// Gathers of one cell record by cell index through a buffer descriptor whose
+// stride is the record size: the load unit scales the index and checks it
+// against the record count (an index past the end reads zeros), so the walk
+// spends no vector instructions on addresses.  The descriptor's last word is
+// the hardware's buffer format for gfx9-family chips (32-bit data format).
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef int32_t amr_i32x2 __attribute__((ext_vector_type(2)));
+typedef float amr_f32x4 __attribute__((ext_vector_type(4)));
+__device__ amr_i32x2 amr_buf_load_i32x2(__amdgpu_buffer_rsrc_t rsrc, int32_t index, int32_t voffset, int32_t soffset,
+                                        int32_t aux) __asm("llvm.amdgcn.struct.ptr.buffer.load.v2i32");
+__device__ amr_f32x4 amr_buf_load_f32x4(__amdgpu_buffer_rsrc_t rsrc, int32_t index, int32_t voffset, int32_t soffset,
+                                        int32_t aux) __asm("llvm.amdgcn.struct.ptr.buffer.load.v4f32");
+constexpr int32_t kBufFormatWord = 0x00020000;
+template <class T>
+__device__ inline __amdgpu_buffer_rsrc_t amr_records(const T AMR_GLOBAL* p, int64_t n) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)sizeof(T), (int)(n < 0x7fffffff ? n : 0x7fffffff),
+                                           kBufFormatWord);
+}
+#endif
+
 // Per-ray constants in mirrored coordinates.
 struct Ray {
   int32_t o[3];    // mirrored origin
@@ -447,8 +467,9 @@ AMR_HD int32_t walk(const TreeView& T, const Ray& R, Entry& E, int max_level, Vi
 }
 
 // Three-input bitwise operations.  On gfx950 the three-input logic
-// instruction issues at the full rate of a two-input one, where the
-// compiler's own choices (or3, bfi) issue at half rate.
+// instruction issues at about 0.6 of the rate of a two-input one, where the
+// compiler's own choices (or3, bfi) issue at half rate (as do two two-input
+// operations in a row).
 #if defined(__HIP_DEVICE_COMPILE__)
 __device__ inline uint32_t or3(uint32_t a, uint32_t b, uint32_t c) { return __builtin_amdgcn_bitop3_b32(a, b, c, 0xFE); }
 // bits of a where m is set, of b elsewhere
@@ -552,13 +573,23 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
   // of each step: the base-level cell, or the previous cell's sibling)
   int lvl = b0;
   int32_t node = offb + (int32_t)((mb ^ fm) & mask3);
+#if defined(__HIP_DEVICE_COMPILE__)
+  const __amdgpu_buffer_rsrc_t cvr = amr_records(T.cv, T.ncells);
+#endif
   for (;;) {
     AMR_CHECK_CELL(T, node);
     float v0;
     for (;;) {
+#if defined(__HIP_DEVICE_COMPILE__)
+      const amr_i32x2 rec = amr_buf_load_i32x2(cvr, node, 0, 0, 0);
+      const int32_t w = rec[0];
+      const int32_t vbits = rec[1];
+      v0 = __int_as_float(vbits);
+#else
       const ChildVal rec = T.cv[(uint32_t)node];
       v0 = rec.v0;
       const int32_t w = rec.child;
+#endif
       if (lvl >= max_level || w < 0) {
         if constexpr (TracksCut<Vis>::value) vis.cut_and &= w;  // sign bit clears at a cut
         break;
@@ -737,17 +768,30 @@ struct WMeanVisT {
   const float AMR_GLOBAL* f1;
   const float AMR_GLOBAL* f2;
   const Cell4 AMR_GLOBAL* pk = nullptr;  // weight = field 0, velocity = fields 1..3, interleaved
+  int64_t npk = 0;                       // records at pk
+  AMR_HD void use_packed(const TreeView& T) {
+    pk = T.packed;
+    npk = T.ncells;
+  }
   float dh[3];
   int los;
   float sw = 0.0f, cw = 0.0f, sf = 0.0f, cf = 0.0f;
   float xw = 0.0f, x0 = 0.0f, x1 = 0.0f, x2 = 0.0f;
   AMR_HD void fetch(int32_t node) {
     if (kPackedLos || pk) {
+#if defined(__HIP_DEVICE_COMPILE__)
+      const amr_f32x4 q = amr_buf_load_f32x4(amr_records(pk, npk), node, 0, 0, 0);
+      xw = q[0];
+      x0 = q[1];
+      x1 = q[2];
+      x2 = q[3];
+#else
       const Cell4 q = pk[(uint32_t)node];
       xw = q.f0;
       x0 = q.f1;
       x1 = q.f2;
       x2 = q.f3;
+#endif
       return;
     }
     xw = w[(uint32_t)node];
@@ -926,7 +970,7 @@ AMR_HD void render_pixel(const TreeView& T, const CameraView& C, int field, int 
     v.f1 = los ? v.f0 + nc : v.f0;
     v.f2 = los ? v.f0 + 2 * nc : v.f0;
     v.los = los;
-    if (packed_los(T, field, wfield, los)) v.pk = T.packed;
+    if (packed_los(T, field, wfield, los)) v.use_packed(T);
     v.dh[0] = v.dh[1] = v.dh[2] = 0.0f;
     if (hit) {
       const float n = sqrtf((float)(R.d64[0] * R.d64[0] + R.d64[1] * R.d64[1] + R.d64[2] * R.d64[2]));
@@ -1174,7 +1218,7 @@ AMR_HD void walk_span(const TreeView& T, const Ray& R, Entry& E, int max_level, 
     v.f1 = los ? v.f0 + nc : v.f0;
     v.f2 = los ? v.f0 + 2 * nc : v.f0;
     v.los = los;
-    if (kStd || packed_los(T, field, wfield, los)) v.pk = T.packed;
+    if (kStd || packed_los(T, field, wfield, los)) v.use_packed(T);
     const float n = sqrtf((float)(R.d64[0] * R.d64[0] + R.d64[1] * R.d64[1] + R.d64[2] * R.d64[2]));
     AMR_UNROLL
     for (int k = 0; k < 3; ++k) v.dh[k] = (float)R.d64[k] / n;
