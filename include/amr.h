@@ -186,7 +186,9 @@ typedef struct {
  *   SUM   sum of v * chord (box units); 0 for rays that miss the box.
  *   MAX   maximum of v; -inf for rays that miss the box.
  *   WMEAN sum(w f chord) / sum(w chord), 0 when the weight integral is 0.
- * aux: device fp32 H x W or NULL; for WMEAN receives sum(w chord).
+ * aux: device fp32 H x W or NULL; for WMEAN receives sum(w chord), computed
+ *   with the SUM projection's arithmetic, so it equals the SUM image of the
+ *   weight field bit for bit (same variant).
  * Cell decisions are exact integer predicates, so the cell sequence of
  * every ray is deterministic; sums are fp32 Kahan-compensated; chord
  * lengths come from an exact integer numerator, in fp64 for cells at level

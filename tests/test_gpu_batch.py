@@ -172,3 +172,46 @@ def test_batched_disk_snapshots_match_oracle_on_sampled_rays():
                 worst = max(worst, parity.check_wmean(got, auxs[k].cpu().numpy()[r], ref, f"image {k}"))
         log(op, "batch of", len(pairs), "images:", len(checked), "checked on 1% samples, worst", f"{worst:.2e}")
         B.close()
+
+
+def test_weight_plane_of_wmean_is_the_sum_projection_of_the_weight():
+    """The weighted mean accumulates the weight integral with exactly the sum
+    projection's arithmetic (product of the cell's weight and the chord,
+    Kahan-added in walk order, spans merged alike), so its weight plane is
+    the sum image of the weight field bit for bit: for the specialised and
+    the general kernels, every batch configuration and the single-image
+    variants."""
+    import paper_1210_8014_amd as amr
+
+    trees, cams, pairs = _mixed_batch()
+    pairs = [p for p in pairs if p[0] > 0]  # the disks (four fields)
+    for los in (True, False):
+        kw = dict(field=1, weight=0, los=los)
+        sums = [torch.empty(cams[c].W * cams[c].H, device="cuda") for _, c in pairs]
+        means = [torch.empty_like(x) for x in sums]
+        weights = [torch.empty_like(x) for x in sums]
+        S = amr.Batch(trees, cams, pairs, amr.SUM, sums, field=0)
+        M = amr.Batch(trees, cams, pairs, amr.WMEAN, means, weights, **kw)
+        for cfg in range(len(amr.batch_configs())):
+            S.set_config(cfg)
+            M.set_config(cfg)
+            for x in sums + weights:
+                x.fill_(-7.0)
+            S.run()
+            M.run()
+            torch.cuda.synchronize()
+            for k, (s, w) in enumerate(zip(sums, weights)):
+                assert torch.equal(s.view(torch.int32), w.view(torch.int32)), \
+                    f"los {los} config {amr.batch_configs()[cfg]} image {k}"
+        S.close()
+        M.close()
+        for v in range(len(amr.variants())):
+            for (t, c) in pairs[:4]:
+                s = torch.empty(cams[c].W * cams[c].H, device="cuda")
+                m, w = torch.empty_like(s), torch.empty_like(s)
+                amr.render(trees[t], cams[c], amr.SUM, s, variant=v, field=0)
+                amr.render(trees[t], cams[c], amr.WMEAN, m, w, variant=v, **kw)
+                torch.cuda.synchronize()
+                assert torch.equal(s.view(torch.int32), w.view(torch.int32)), \
+                    f"los {los} variant {amr.variants()[v]} tree {t} camera {c}"
+        log("los", los, "weight plane equals the sum image on", len(pairs), "images")
