@@ -109,7 +109,7 @@ def variant_kernel(variant_name: str, op: str, max_level: int, W: int, H: int):
         return "k_render_split<%d, %d, %d, %s>" % (code, k, remap, "true" if std else "false"), packets * 64 * k
     pw = int(variant_name[1:].split("x")[0])
     wpb = int(variant_name.split("_w")[1].split("_")[0])
-    mode = {"base": 0, "stack": 1, "fast": 2}[variant_name.split("_")[2]]
+    mode = {"base": 0, "stack": 1, "fast": 2, "fastlds": 3}[variant_name.split("_")[2]]
     packets = ((W + pw - 1) // pw) * ((H + 64 // pw - 1) // (64 // pw))
     blocks = (packets + wpb - 1) // wpb
     return "k_render<%d, %d, %d, %d, %d>" % (code, pw, wpb, remap, mode), blocks * 64 * wpb

@@ -37,6 +37,15 @@ struct LdsStack {
   __device__ int32_t get(int l) const { return base[(l - lo) * stride]; }
   __device__ void set(int l, int32_t v) { base[(l - lo) * stride] = v; }
 };
+// The same with the block size as a compile-time stride (the fast walk's
+// stack: levels above lo only).
+template <int STRIDE>
+struct LdsStackT {
+  int32_t* base;  // this thread's entry of level lo
+  int lo;
+  __device__ int32_t get(int l) const { return base[(l - lo) * STRIDE]; }
+  __device__ void set(int l, int32_t v) { base[(l - lo) * STRIDE] = v; }
+};
 
 template <int OP, int PW, int WPB, int REMAP, int MODE>
 __global__ __launch_bounds__(64 * WPB) void k_render(RenderArgs A) {
@@ -54,6 +63,10 @@ __global__ __launch_bounds__(64 * WPB) void k_render(RenderArgs A) {
   float o = 0.0f, x = 0.0f;
   if (MODE == kWalkStack) {
     LdsStack S{lds + threadIdx.x, (int)blockDim.x, A.t.base < A.max_level ? A.t.base : A.max_level};
+    render_pixel<OP, MODE>(A.t, A.c, A.field, A.wfield, A.los, A.max_level, i, j, o, x, S);
+  } else if (MODE == kWalkFastStack) {
+    const int lo = A.t.base < A.max_level ? A.t.base : A.max_level;
+    LdsStackT<64 * WPB> S{lds + threadIdx.x, lo};
     render_pixel<OP, MODE>(A.t, A.c, A.field, A.wfield, A.los, A.max_level, i, j, o, x, S);
   } else {
     NoStack S;
@@ -186,6 +199,7 @@ constexpr Variant kVariants[] = {
     {8, 4, kRemapXcd, kWalkFast, "p8x8_w4_fast_xcdband"}, {8, 2, kRemapNone, kWalkFast, "p8x8_split2_fast"},
     {8, 4, kRemapNone, kWalkFast, "p8x8_split4_fast"},    {8, 1, kRemapCenter, kWalkFast, "p8x8_w1_fast_center"},
     {8, 2, kRemapCenter, kWalkFast, "p8x8_split2_fast_center"},
+    {8, 4, kRemapNone, kWalkFastStack, "p8x8_w4_fastlds"},  {8, 2, kRemapNone, kWalkFastStack, "p8x8_w2_fastlds"},
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -194,7 +208,9 @@ hipError_t launch_one(const RenderArgs& a, hipStream_t s) {
   const int64_t packets = (int64_t)a.packets_x * a.packets_y;
   const int64_t blocks = (packets + WPB - 1) / WPB;
   const int b0 = a.t.base < a.max_level ? a.t.base : a.max_level;
-  const size_t lds = MODE == kWalkStack ? (size_t)(a.max_level - b0 + 1) * 64 * WPB * sizeof(int32_t) : 0;
+  const size_t lds = (MODE == kWalkStack || MODE == kWalkFastStack)
+                        ? (size_t)(a.max_level - b0 + 1) * 64 * WPB * sizeof(int32_t)
+                        : 0;
   hipLaunchKernelGGL((k_render<OP, PW, WPB, REMAP, MODE>), dim3((unsigned)blocks), dim3(64 * WPB), lds, s, a);
   return hipGetLastError();
 }
@@ -225,6 +241,8 @@ hipError_t launch_op(int v, const RenderArgs& a, hipStream_t s) {
     case 10: return launch_split<OP, 4>(a, s);
     case 11: return launch_one<OP, 8, 1, kRemapCenter, kWalkFast>(a, s);
     case 12: return launch_split<OP, 2, kRemapCenter>(a, s);
+    case 13: return launch_one<OP, 8, 4, kRemapNone, kWalkFastStack>(a, s);
+    case 14: return launch_one<OP, 8, 2, kRemapNone, kWalkFastStack>(a, s);
     default: return hipErrorInvalidValue;
   }
 }

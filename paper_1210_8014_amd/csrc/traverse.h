@@ -538,8 +538,15 @@ struct NeedsParams<V, decltype((void)V::kNeedsParams)> {
 };
 
 // kShallow: the caller guarantees max_level < kDeepLevel (no fp64 chords).
-template <class Vis, bool kWholeBox = false, bool kShallow = false>
-AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_level, Vis& vis) {
+// Stk: with a stack other than NoStack (get / set of one int32 per level,
+// levels above min(base, max_level)), every descent step records the
+// first-child index of the cell it leaves, and a move whose deepest common
+// ancestor lies below the base level restarts at that ancestor's child
+// instead of at the base level (fewer dependent loads on deep trees; the
+// same cells, in the same order, with the same chords).
+template <class Vis, bool kWholeBox = false, bool kShallow = false, class Stk = NoStack>
+AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_level, Vis& vis, Stk& stk) {
+  constexpr bool kStk = !std::is_same<Stk, NoStack>::value;
   const int b0 = T.base < max_level ? T.base : max_level;
   const int sb = kFix - b0;
   // Direction components, 0 on an axis the ray does not move along: in the
@@ -596,6 +603,7 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
       }
       pfc = w;
       ++lvl;
+      if constexpr (kStk) stk.set(lvl, w);
       const int s = kFix - lvl;
       if (lvl > E.lam) {
         // entry numerator, kept inside this rarely taken branch (hoisted, its
@@ -717,11 +725,27 @@ AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_leve
         lvl = jr + 1;
         continue;
       }
+      if constexpr (kStk) {
+        // the ancestor at level jr is shared (no carry reached the base
+        // level, so the base cell is unchanged): restart at its child
+        if (jr >= b0) {
+          pfc = stk.get(jr + 1);
+          node = pfc + (int32_t)(octant_bits(E.p[0], E.p[1], E.p[2], kFix - 1 - jr) ^ (fm & 7u));
+          lvl = jr + 1;
+          continue;
+        }
+      }
       node = offb + (int32_t)((mb ^ fm) & mask3);
     }
     lvl = b0;
   }
   return nseg;
+}
+
+template <class Vis, bool kWholeBox = false, bool kShallow = false>
+AMR_HD int32_t walk_fast(const TreeView& T, const Ray& R, Entry& E, int max_level, Vis& vis) {
+  NoStack none;
+  return walk_fast<Vis, kWholeBox, kShallow, NoStack>(T, R, E, max_level, vis, none);
 }
 
 template <class Vis>
@@ -938,13 +962,15 @@ AMR_HD bool std_walk(int op, const TreeView& T, int field, int wfield, int los, 
 // The whole per-pixel computation of one projection; out receives the
 // pixel value, aux (WMEAN) the weight integral.
 // Descent modes: restart at the complete base level (kWalkBase), at the
-// common ancestor kept in a stack (kWalkStack), or the register-cached
-// form (kWalkFast).  All three meet the same cells with the same chords.
-enum { kWalkBase = 0, kWalkStack = 1, kWalkFast = 2 };
+// common ancestor kept in a stack (kWalkStack), the register-cached form
+// (kWalkFast), or that form with an ancestor stack (kWalkFastStack).  All
+// meet the same cells with the same chords.
+enum { kWalkBase = 0, kWalkStack = 1, kWalkFast = 2, kWalkFastStack = 3 };
 
 template <int MODE, class Vis, class Stack>
 AMR_HD int32_t walk_mode(const TreeView& T, const Ray& R, Entry& E, int max_level, Vis& v, Stack& S) {
-  if (MODE == kWalkFast) return walk_fast<Vis, true>(T, R, E, max_level, v);
+  if constexpr (MODE == kWalkFast) return walk_fast<Vis, true>(T, R, E, max_level, v);
+  if constexpr (MODE == kWalkFastStack) return walk_fast<Vis, true, false, Stack>(T, R, E, max_level, v, S);
   return walk<MODE == kWalkStack>(T, R, E, max_level, v, S);
 }
 

@@ -79,6 +79,10 @@ int emu_render(const int32_t* child, const float* val, int64_t ncells, int32_t n
       if (op == 0) render_pixel<kOpSum, kWalkStack>(T, C, field, wfield, los, max_level, i, j, o, x, S);
       else if (op == 1) render_pixel<kOpMax, kWalkStack>(T, C, field, wfield, los, max_level, i, j, o, x, S);
       else render_pixel<kOpWMean, kWalkStack>(T, C, field, wfield, los, max_level, i, j, o, x, S);
+    } else if (lca == 3) {
+      if (op == 0) render_pixel<kOpSum, kWalkFastStack>(T, C, field, wfield, los, max_level, i, j, o, x, S);
+      else if (op == 1) render_pixel<kOpMax, kWalkFastStack>(T, C, field, wfield, los, max_level, i, j, o, x, S);
+      else render_pixel<kOpWMean, kWalkFastStack>(T, C, field, wfield, los, max_level, i, j, o, x, S);
     } else if (lca == 2) {
       if (op == 0) render_pixel<kOpSum, kWalkFast>(T, C, field, wfield, los, max_level, i, j, o, x, S);
       else if (op == 1) render_pixel<kOpMax, kWalkFast>(T, C, field, wfield, los, max_level, i, j, o, x, S);

@@ -14,9 +14,9 @@ from tests.test_oracle_pins import degenerate_cams, rand_cams
 
 
 class EmuRenderer:
-    """Renders with all three descent modes (restart at the base level, at the
-    common ancestor from a stack, register-cached) and insists they are
-    bit-identical."""
+    """Renders with all four descent modes (restart at the base level, at the
+    common ancestor from a stack, register-cached, register-cached with an
+    ancestor stack) and insists they are bit-identical."""
 
     def __init__(self, leaves, restrict=None):
         self.T = amr.Tree(leaves, restrict=restrict, host_only=True)
@@ -27,7 +27,7 @@ class EmuRenderer:
 
     def render(self, cam, op, field=0, weight=0, los=False, rays=None):
         a = self.E.render(cam, op, field, weight, los, rays, lca=2)
-        for mode in (0, 1):
+        for mode in (0, 1, 3):
             b = self.E.render(cam, op, field, weight, los, rays, lca=mode)
             for x, y in zip(a, b):
                 assert np.array_equal(x.view(np.int32), y.view(np.int32)), f"descent mode {mode} differs"

@@ -13,7 +13,7 @@ import paper_1210_8014_amd as amr
 # remap: None, "xcd" (bands over the 8 XCDs) or "center" (packet rows from the middle out)
 VARIANTS = [(8, 1, None, 1), (8, 2, None, 1), (8, 4, None, 1), (16, 4, None, 1), (32, 2, None, 1),
             (8, 1, None, 1), (8, 4, None, 1), (8, 1, None, 1), (8, 4, "xcd", 1), (8, 2, None, 2), (8, 4, None, 4),
-            (8, 1, "center", 1), (8, 2, "center", 2)]
+            (8, 1, "center", 1), (8, 2, "center", 2), (8, 4, None, 1), (8, 2, None, 1)]
 
 
 def xcd_remap(b, nb):
