@@ -37,15 +37,6 @@ struct LdsStack {
   __device__ int32_t get(int l) const { return base[(l - lo) * stride]; }
   __device__ void set(int l, int32_t v) { base[(l - lo) * stride] = v; }
 };
-// The same with the block size as a compile-time stride (the fast walk's
-// stack: levels above lo only).
-template <int STRIDE>
-struct LdsStackT {
-  int32_t* base;  // this thread's entry of level lo
-  int lo;
-  __device__ int32_t get(int l) const { return base[(l - lo) * STRIDE]; }
-  __device__ void set(int l, int32_t v) { base[(l - lo) * STRIDE] = v; }
-};
 
 template <int OP, int PW, int WPB, int REMAP, int MODE>
 __global__ __launch_bounds__(64 * WPB) void k_render(RenderArgs A) {
@@ -66,7 +57,7 @@ __global__ __launch_bounds__(64 * WPB) void k_render(RenderArgs A) {
     render_pixel<OP, MODE>(A.t, A.c, A.field, A.wfield, A.los, A.max_level, i, j, o, x, S);
   } else if (MODE == kWalkFastStack) {
     const int lo = A.t.base < A.max_level ? A.t.base : A.max_level;
-    LdsStackT<64 * WPB> S{lds + threadIdx.x, lo};
+    StridedStack<64 * WPB> S{lds + threadIdx.x, lo};
     render_pixel<OP, MODE>(A.t, A.c, A.field, A.wfield, A.los, A.max_level, i, j, o, x, S);
   } else {
     NoStack S;

@@ -248,6 +248,7 @@ __global__ __launch_bounds__(256) void k_stream_init(Partial* acc, int64_t n) {
 // added to the pixel's partial.
 template <int OP, bool kStd>
 __global__ __launch_bounds__(64) void k_stream_chunk(StreamArgs a) {
+  extern __shared__ int32_t stack_lds[];  // the walk's ancestor stack
   const int lane = threadIdx.x;
   const int ty = (int)blockIdx.x / a.px, tx = (int)blockIdx.x - ty * a.px;
   const int di = tx * 8 + (lane & 7), dj = ty * 8 + (lane >> 3);
@@ -259,7 +260,8 @@ __global__ __launch_bounds__(64) void k_stream_chunk(StreamArgs a) {
   if (!cube_clip(R, E, a.lc, a.cx, a.cy, a.cz)) return;
   Partial P;
   partial_init<OP>(P);
-  walk_span<OP, false, false, kStd>(a.t, R, E, a.max_level, a.field, a.wfield, a.los, P);
+  StridedStack<64> S{stack_lds + lane, a.t.base < a.max_level ? a.t.base : a.max_level};
+  walk_span<OP, false, false, kStd>(a.t, R, E, a.max_level, a.field, a.wfield, a.los, P, nullptr, S);
   Partial* A = a.acc + (int64_t)j * a.c.W + i;
   Partial Q = *A;
   partial_merge<OP>(Q, P);
@@ -282,7 +284,9 @@ __global__ __launch_bounds__(256) void k_stream_finish(const Partial* acc, float
 
 template <int OP, bool kStd>
 void launch_chunk(const StreamArgs& a, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_stream_chunk<OP, kStd>), dim3((unsigned)blocks), dim3(64), 0, s, a);
+  const int b0 = a.t.base < a.max_level ? a.t.base : a.max_level;
+  const size_t lds = (size_t)(a.max_level - b0 + 1) * 64 * sizeof(int32_t);
+  hipLaunchKernelGGL((k_stream_chunk<OP, kStd>), dim3((unsigned)blocks), dim3(64), lds, s, a);
 }
 
 }  // namespace

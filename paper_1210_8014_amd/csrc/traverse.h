@@ -1217,15 +1217,16 @@ AMR_HD void take_cut(const V& v, bool* cut) {
 // max_level < kDeepLevel (no per-cell tests of the layout, nor for sum and
 // max of the chord precision; measured, the wmean walk is faster with that
 // test kept).
-template <int OP, bool kWholeBox = false, bool kCut = false, bool kStd = false>
+// Stk: an ancestor stack for walk_fast (NoStack: none).
+template <int OP, bool kWholeBox = false, bool kCut = false, bool kStd = false, class Stk = NoStack>
 AMR_HD void walk_span(const TreeView& T, const Ray& R, Entry& E, int max_level, int field, int wfield, int los,
-                      Partial& P, bool* cut = nullptr) {
+                      Partial& P, bool* cut, Stk& stk) {
   const int64_t nc = T.ncells;
   if (OP == kOpSum) {
     CutIf<kCut, SumVisT<kStd>> v;
     v.v = T.val + (int64_t)field * nc;
     v.field0 = field == 0;
-    walk_fast<decltype(v), kWholeBox, kStd>(T, R, E, max_level, v);
+    walk_fast<decltype(v), kWholeBox, kStd, Stk>(T, R, E, max_level, v, stk);
     P.s0 = v.s;
     P.c0 = v.c;
     take_cut(v, cut);
@@ -1234,7 +1235,7 @@ AMR_HD void walk_span(const TreeView& T, const Ray& R, Entry& E, int max_level, 
     v.v = T.val + (int64_t)field * nc;
     v.m = -INFINITY;
     v.field0 = field == 0;
-    walk_fast<decltype(v), kWholeBox, kStd>(T, R, E, max_level, v);
+    walk_fast<decltype(v), kWholeBox, kStd, Stk>(T, R, E, max_level, v, stk);
     P.s0 = v.m;
     take_cut(v, cut);
   } else {
@@ -1248,7 +1249,7 @@ AMR_HD void walk_span(const TreeView& T, const Ray& R, Entry& E, int max_level, 
     const float n = sqrtf((float)(R.d64[0] * R.d64[0] + R.d64[1] * R.d64[1] + R.d64[2] * R.d64[2]));
     AMR_UNROLL
     for (int k = 0; k < 3; ++k) v.dh[k] = (float)R.d64[k] / n;
-    walk_fast<decltype(v), kWholeBox>(T, R, E, max_level, v);
+    walk_fast<decltype(v), kWholeBox, false, Stk>(T, R, E, max_level, v, stk);
     P.s0 = v.sw;
     P.c0 = v.cw;
     P.s1 = v.sf;
@@ -1256,6 +1257,24 @@ AMR_HD void walk_span(const TreeView& T, const Ray& R, Entry& E, int max_level, 
     take_cut(v, cut);
   }
 }
+
+template <int OP, bool kWholeBox = false, bool kCut = false, bool kStd = false>
+AMR_HD void walk_span(const TreeView& T, const Ray& R, Entry& E, int max_level, int field, int wfield, int los,
+                      Partial& P, bool* cut = nullptr) {
+  NoStack none;
+  walk_span<OP, kWholeBox, kCut, kStd, NoStack>(T, R, E, max_level, field, wfield, los, P, cut, none);
+}
+
+// A per-thread ancestor stack in LDS, laid out [level][thread] (STRIDE
+// threads per block) so that a wave's 64 lanes touch 64 consecutive words;
+// levels lo + 1 .. max_level.
+template <int STRIDE>
+struct StridedStack {
+  int32_t* base;  // this thread's word of level lo
+  int lo;
+  AMR_HD int32_t get(int l) const { return base[(l - lo) * STRIDE]; }
+  AMR_HD void set(int l, int32_t v) { base[(l - lo) * STRIDE] = v; }
+};
 
 // P += Q (Q is the next span along the ray).
 template <int OP>
