@@ -251,7 +251,9 @@ def test_gpu_deepzoom_full_size_sampled():
     """Deep zoom at full size: ~201M leaves to level 22, the eye inside the disk
     2^-9 box from core 0, 4096^2 pixels, automatic maximum level 21, so cells
     at levels 18..21 (FP64 chords) are crossed.  Sum and max on a seeded 1% ray
-    sample for the default and the unsplit walk; cell sequences of 1500 rays;
+    sample for the default, the unsplit walk and the unsplit walk with an
+    ancestor stack (also bit-identical to the stackless one over the whole
+    image); cell sequences of 1500 rays;
     the streamed render of the same image from the tree in host memory, in
     the bench's configuration, on the same sample (max also bit-identical to
     the in-memory render); slices at levels 22, 21 and 18."""
@@ -277,12 +279,17 @@ def test_gpu_deepzoom_full_size_sampled():
     assert cam.max_level == 21
     n = cam.W * cam.H
     rays = np.sort(np.random.default_rng(5).choice(n, n // 100, replace=False))
-    for v in (-1, 0):
+    lds = amr.variants().index("p8x8_w4_fastlds")  # the walk with an ancestor stack (the deep zoom's tuned choice)
+    for v in (-1, 0, lds):
         R.variant = v
         log("variant", v)
         res = parity.compare_all(R, OT, camd, ops=("sum", "max"), rays=rays,
                                  trace_rays=rays[::112] if v == -1 else None, what=f"deepzoom v{v}")
         log("  worst sum rel", res["sum"])
+    for op in (amr.SUM, amr.MAX):
+        a, _ = R.full(cam, op, variant=0)
+        b, _ = R.full(cam, op, variant=lds)
+        assert np.array_equal(a.view(np.int32), b.view(np.int32)), "stack walk differs from the stackless walk"
     offs, cells = R.trace(cam, rays[::112])
     assert cells[:, 0].max() >= 18
     ocam = OT.camera(camd)
