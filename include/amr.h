@@ -205,7 +205,10 @@ amr_status amr_render(const amr_tree* t, const amr_camera* cam, amr_op op, const
 
 /* Number of kernel variants (ray-packet shape, waves per block, descent
  * mode, spans per ray, dispatch order) amr_render_opts.variant may select, a
- * short name for each, and the one used when none is selected or tuned. */
+ * short name for each, and the one used when none is selected or tuned.
+ * That default holds while the camera's maximum level lies fewer than 10
+ * levels below the tree's complete base level; deeper, amr_render takes
+ * p8x8_w4_fastlds (the walk with an ancestor stack) instead. */
 int32_t amr_variant_count(void);
 const char* amr_variant_name(int32_t v);
 int32_t amr_variant_default(void);

@@ -552,7 +552,16 @@ amr_status amr_render(const amr_tree* t, const amr_camera* cam, amr_op op, const
   if (o.field < 0 || o.field + ((op == AMR_WMEAN && o.los_velocity) ? 2 : 0) >= nf)
     return fail(AMR_EINVAL, "field index out of range");
   if (op == AMR_WMEAN && (o.weight_field < 0 || o.weight_field >= nf)) return fail(AMR_EINVAL, "bad weight field");
-  int v = o.variant >= 0 ? o.variant : (t->tuned_variant[op] >= 0 ? t->tuned_variant[op] : default_variant());
+  // untuned: the default variant, or for a maximum level 10 or more levels
+  // below the complete base level (most moves re-descend several levels) the
+  // walk with an ancestor stack, which shortens those re-descents (deep zoom,
+  // 11 levels: 34.9 ms against 39.8 ms stackless and 62.8 ms split)
+  const int b0 = std::min(t->view.base, cam->max_level);
+  int untuned = default_variant();
+  if (cam->max_level - b0 >= 10)
+    for (int k = 0; k < variant_count(); ++k)
+      if (std::strcmp(variant_name(k), "p8x8_w4_fastlds") == 0) untuned = k;
+  int v = o.variant >= 0 ? o.variant : (t->tuned_variant[op] >= 0 ? t->tuned_variant[op] : untuned);
   if (v >= variant_count()) return fail(AMR_EINVAL, "bad variant");
   RenderArgs a;
   a.t = t->view;

@@ -290,6 +290,9 @@ def test_gpu_deepzoom_full_size_sampled():
         a, _ = R.full(cam, op, variant=0)
         b, _ = R.full(cam, op, variant=lds)
         assert np.array_equal(a.view(np.int32), b.view(np.int32)), "stack walk differs from the stackless walk"
+        # 11 levels below the base level: the untuned default is the stack walk
+        c, _ = R.full(cam, op, variant=-1)
+        assert np.array_equal(b.view(np.int32), c.view(np.int32)), "deep default is not the stack walk"
     offs, cells = R.trace(cam, rays[::112])
     assert cells[:, 0].max() >= 18
     ocam = OT.camera(camd)
