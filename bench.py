@@ -83,10 +83,11 @@ def batch_kernel_name(config: str, op: str) -> str:
     """Kernel a batch launch shape runs for op on these workloads (as
     rocprofv3 names it): sum and max of density and the line-of-sight
     velocity weighted by density have the common field layout, so the grid
-    shapes run their specialised walk."""
+    shapes run their specialised walk; their trees lie fewer than 10 levels
+    below the base level, so without the ancestor stack."""
     code = {"sum": 0, "max": 1, "wmean": 2}[op]
     if "grid" in config:
-        return "k_batch_grid<%d, %d, true>" % (code, 2 if "split2" in config else 1)
+        return "k_batch_grid<%d, %d, true, false>" % (code, 2 if "split2" in config else 1)
     return "k_batch<%d, ...> (%s)" % (code, config)
 
 

@@ -95,10 +95,12 @@ __global__ __launch_bounds__(64) void k_batch(const BatchImage* __restrict__ img
 // One block per packet of all images (images largest first, so the long
 // pieces start early); K waves walk the K spans of each ray and merge in LDS.
 // STD: every image may take walk_span's kStd walk (std_walk).
-template <int OP, int K, bool STD = false>
+// STK: the walk keeps an ancestor stack in dynamic LDS (deep batches).
+template <int OP, int K, bool STD = false, bool STK = false>
 __global__ __launch_bounds__(64 * K) void k_batch_grid(const BatchImage* __restrict__ imgs,
                                                       const int64_t* __restrict__ begin, int32_t nimg) {
   __shared__ float part[(K > 1 ? K - 1 : 1) * 4 * 64];
+  extern __shared__ int32_t stack_lds[];  // STK: (levels) x 64K words
   const int lane = threadIdx.x & 63, w = (int)(threadIdx.x >> 6);
   const int64_t p = blockIdx.x;
   int lo = 0, hi = nimg - 1;
@@ -118,10 +120,18 @@ __global__ __launch_bounds__(64 * K) void k_batch_grid(const BatchImage* __restr
   Entry E;
   if (in && setup_ray(I.c, i, j, R, E) && span_setup(R, E, b0, K, w)) {
     // the last span (the whole ray when K = 1) runs to the box: one-comparison end test
-    if (K == 1 || w == K - 1)
-      walk_span<OP, true, false, STD>(I.t, R, E, I.max_level, I.field, I.wfield, I.los, P);
-    else
-      walk_span<OP, false, false, STD>(I.t, R, E, I.max_level, I.field, I.wfield, I.los, P);
+    if constexpr (STK) {
+      StridedStack<64 * K> S{stack_lds + threadIdx.x, b0};
+      if (K == 1 || w == K - 1)
+        walk_span<OP, true, false, STD>(I.t, R, E, I.max_level, I.field, I.wfield, I.los, P, nullptr, S);
+      else
+        walk_span<OP, false, false, STD>(I.t, R, E, I.max_level, I.field, I.wfield, I.los, P, nullptr, S);
+    } else {
+      if (K == 1 || w == K - 1)
+        walk_span<OP, true, false, STD>(I.t, R, E, I.max_level, I.field, I.wfield, I.los, P);
+      else
+        walk_span<OP, false, false, STD>(I.t, R, E, I.max_level, I.field, I.wfield, I.los, P);
+    }
   }
   if (K > 1) {
     if (w > 0) {
@@ -169,18 +179,29 @@ __global__ void k_zero_counter(unsigned long long* c) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0;
 }
 
+template <int OP, bool STD, bool STK>
+void launch_grid(int split, int64_t total, int stack_levels, const BatchImage* imgs, const int64_t* begin, int nimg,
+                 hipStream_t s) {
+  const size_t lds = STK ? (size_t)stack_levels * 64 * split * sizeof(int32_t) : 0;
+  if (split == 2)
+    hipLaunchKernelGGL((k_batch_grid<OP, 2, STD, STK>), dim3((unsigned)total), dim3(128), lds, s, imgs, begin, nimg);
+  else
+    hipLaunchKernelGGL((k_batch_grid<OP, 1, STD, STK>), dim3((unsigned)total), dim3(64), lds, s, imgs, begin, nimg);
+}
+
+// stack_levels > 0: the deepest image's maximum level lies kDeepSpan or
+// more levels below its base level; the grid kernels then keep an ancestor
+// stack of that many levels per thread.
 template <int OP>
 hipError_t launch_batch_op(const BatchConfig& cfg, const BatchImage* imgs, const int64_t* begin, int nimg,
-                           int64_t total, unsigned long long* counter, int grid, bool std_layout, hipStream_t s) {
-  if (std_layout && cfg.split == 2)
-    hipLaunchKernelGGL((k_batch_grid<OP, 2, true>), dim3((unsigned)total), dim3(128), 0, s, imgs, begin, nimg);
-  else if (std_layout && cfg.split == 1)
-    hipLaunchKernelGGL((k_batch_grid<OP, 1, true>), dim3((unsigned)total), dim3(64), 0, s, imgs, begin, nimg);
-  else if (cfg.split == 2)
-    hipLaunchKernelGGL((k_batch_grid<OP, 2>), dim3((unsigned)total), dim3(128), 0, s, imgs, begin, nimg);
-  else if (cfg.split == 1)
-    hipLaunchKernelGGL((k_batch_grid<OP, 1>), dim3((unsigned)total), dim3(64), 0, s, imgs, begin, nimg);
-  else if (cfg.pw == 8 && cfg.mode == kWalkFast)
+                           int64_t total, unsigned long long* counter, int grid, bool std_layout, int stack_levels,
+                           hipStream_t s) {
+  if (cfg.split > 0) {
+    if (std_layout && stack_levels > 0) launch_grid<OP, true, true>(cfg.split, total, stack_levels, imgs, begin, nimg, s);
+    else if (std_layout) launch_grid<OP, true, false>(cfg.split, total, 0, imgs, begin, nimg, s);
+    else if (stack_levels > 0) launch_grid<OP, false, true>(cfg.split, total, stack_levels, imgs, begin, nimg, s);
+    else launch_grid<OP, false, false>(cfg.split, total, 0, imgs, begin, nimg, s);
+  } else if (cfg.pw == 8 && cfg.mode == kWalkFast)
     hipLaunchKernelGGL((k_batch<OP, 8, kWalkFast>), dim3(grid), dim3(64), 0, s, imgs, begin, nimg, total, counter,
                        cfg.chunk);
   else if (cfg.pw == 16 && cfg.mode == kWalkFast)
@@ -267,12 +288,20 @@ struct amr_batch {
     // the specialised walk when every image has the op's common field layout
     const int o = op == AMR_SUM ? kOpSum : op == AMR_MAX ? kOpMax : kOpWMean;
     bool sl = true;
-    for (const BatchImage& I : host_images) sl = sl && std_walk(o, I.t, I.field, I.wfield, I.los, I.max_level);
+    // and the ancestor stack when the deepest image lies kDeepSpan or more
+    // levels below its base level
+    int span = 0;
+    for (const BatchImage& I : host_images) {
+      sl = sl && std_walk(o, I.t, I.field, I.wfield, I.los, I.max_level);
+      span = std::max(span, I.max_level - std::min(I.t.base, I.max_level));
+    }
+    const int stack_levels = span >= kDeepSpan ? span + 1 : 0;
     if (op == AMR_SUM)
-      return launch_batch_op<kOpSum>(cfg, d_imgs, d_begin, nimg, total_packets, d_counter, grid, sl, s);
+      return launch_batch_op<kOpSum>(cfg, d_imgs, d_begin, nimg, total_packets, d_counter, grid, sl, stack_levels, s);
     if (op == AMR_MAX)
-      return launch_batch_op<kOpMax>(cfg, d_imgs, d_begin, nimg, total_packets, d_counter, grid, sl, s);
-    return launch_batch_op<kOpWMean>(cfg, d_imgs, d_begin, nimg, total_packets, d_counter, grid, sl, s);
+      return launch_batch_op<kOpMax>(cfg, d_imgs, d_begin, nimg, total_packets, d_counter, grid, sl, stack_levels, s);
+    return launch_batch_op<kOpWMean>(cfg, d_imgs, d_begin, nimg, total_packets, d_counter, grid, sl, stack_levels,
+                                     s);
   }
   hipError_t capture() {
     drop_graph();

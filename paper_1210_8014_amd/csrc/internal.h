@@ -72,6 +72,10 @@ int variant_count();
 const char* variant_name(int v);
 int variant_packet_width(int v);
 int default_variant();  // the variant amr_render uses when none is chosen or tuned
+// Trees whose camera maximum level lies this many levels or more below the
+// complete base level are walked with an ancestor stack by default (most
+// moves re-descend several levels there; the stack shortens them).
+constexpr int kDeepSpan = 10;
 
 // Live-tree registry (batch.hip): batches refuse to run on freed trees.
 void register_tree(uint64_t serial);

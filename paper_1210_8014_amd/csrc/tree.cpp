@@ -558,7 +558,7 @@ amr_status amr_render(const amr_tree* t, const amr_camera* cam, amr_op op, const
   // 11 levels: 34.9 ms against 39.8 ms stackless and 62.8 ms split)
   const int b0 = std::min(t->view.base, cam->max_level);
   int untuned = default_variant();
-  if (cam->max_level - b0 >= 10)
+  if (cam->max_level - b0 >= kDeepSpan)
     for (int k = 0; k < variant_count(); ++k)
       if (std::strcmp(variant_name(k), "p8x8_w4_fastlds") == 0) untuned = k;
   int v = o.variant >= 0 ? o.variant : (t->tuned_variant[op] >= 0 ? t->tuned_variant[op] : untuned);

@@ -215,3 +215,37 @@ def test_weight_plane_of_wmean_is_the_sum_projection_of_the_weight():
                 assert torch.equal(s.view(torch.int32), w.view(torch.int32)), \
                     f"los {los} variant {amr.variants()[v]} tree {t} camera {c}"
         log("los", los, "weight plane equals the sum image on", len(pairs), "images")
+
+
+def test_deep_batch_with_ancestor_stack_matches_single_renders():
+    """A batch whose maximum level lies 10 levels below the tree's base level
+    (a disk refined to level 17, base level 7) runs the grid kernels that
+    keep an ancestor stack; every image equals the stackless single render of
+    the same shape bit for bit (sum, max, wmean; both grid shapes)."""
+    import paper_1210_8014_amd as amr
+
+    T = amr.Tree(amrgen.disk(seed=5, lmax=17, m_thr=2e-5))
+    assert T.lmax == 17
+    descs = amrgen.orbit_cameras(6, seed=3, side_lo=96, side_hi=256, multiple=1, max_level=17)
+    cams = [amr.set_camera(d) for d in descs]
+    assert all(c.max_level == 17 for c in cams)
+    pairs = [(0, c) for c in range(len(cams))]
+    split_variant = amr.variants().index("p8x8_split2_fast")
+    for o, kw in ((amr.SUM, {}), (amr.MAX, {}), (amr.WMEAN, dict(field=1, weight=0, los=True))):
+        outs = [torch.full((c.W * c.H,), -7.0, device="cuda") for c in cams]
+        auxs = [torch.full_like(x, -7.0) for x in outs] if o == amr.WMEAN else None
+        B = amr.Batch([T], cams, pairs, o, outs, auxs, **kw)
+        for cfg, variant in (("p8x8_fast_grid", 0), ("p8x8_split2_grid", split_variant)):
+            B.set_config(amr.batch_configs().index(cfg))
+            B.run()
+            torch.cuda.synchronize()
+            for k, c in enumerate(cams):
+                r = torch.empty(c.W * c.H, device="cuda")
+                a = torch.empty_like(r) if o == amr.WMEAN else None
+                amr.render(T, c, o, r, a, variant=variant, **kw)
+                torch.cuda.synchronize()
+                assert torch.equal(r.view(torch.int32), outs[k].view(torch.int32)), f"op {o} {cfg} image {k}"
+                if a is not None:
+                    assert torch.equal(a.view(torch.int32), auxs[k].view(torch.int32)), f"op {o} {cfg} image {k}"
+        B.close()
+        log("deep batch op", o, "matches single renders")
