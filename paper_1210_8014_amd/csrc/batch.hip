@@ -8,7 +8,9 @@
 // 64-ray packets of all images: a wave takes the next chunk of packets until
 // the counter passes the end.  The grid configurations instead give every
 // packet its own block and let the hardware dispatcher hand blocks to free
-// CUs in order.  Images are ordered largest first so the tail holds small
+// CUs in order.  The images of one tree are kept together (so the caches
+// hold one tree's working set at a time; trees with the longest rays first)
+// and ordered largest first within their tree, so the tail holds small
 // pieces.  The launch is captured once into a hipGraph and replayed; the
 // per-pixel code is the same as amr_render's, so every image is bit-identical
 // to its single-image render with the matching variant (unsplit or split).
@@ -358,8 +360,9 @@ amr_status amr_batch_create(const amr_tree* const* trees, int32_t ntrees, const 
     I.packets_x = I.packets_y = 0;
     serials.push_back(t->serial);
   }
-  // Order: images whose longest ray is longest first (a lone wave walking it
-  // sets the end of the launch unless it starts early), then larger first.
+  // Order: by tree (below), then images whose longest ray is longest first (a
+  // lone wave walking it sets the end of the launch unless it starts early),
+  // then larger first.
   std::vector<unsigned> longest(npairs, 0);
   {
     unsigned* d_long = nullptr;
@@ -375,9 +378,18 @@ amr_status amr_batch_create(const amr_tree* const* trees, int32_t ntrees, const 
     if (d_long) (void)hipFree(d_long);
     if (e != hipSuccess) return fail(AMR_EHIP, std::string("batch ordering failed: ") + hipGetErrorString(e));
   }
+  // images of one tree together (trees in the order of their longest ray),
+  // so that the caches hold one tree's working set at a time
+  std::vector<unsigned> tree_longest(ntrees, 0);
+  for (int k = 0; k < npairs; ++k) tree_longest[pairs[2 * k]] = std::max(tree_longest[pairs[2 * k]], longest[k]);
   std::vector<int> order(npairs);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const int ta = pairs[2 * a], tb = pairs[2 * b];
+    if (ta != tb) {
+      if (tree_longest[ta] != tree_longest[tb]) return tree_longest[ta] > tree_longest[tb];
+      return ta < tb;
+    }
     if (longest[a] != longest[b]) return longest[a] > longest[b];
     return (int64_t)imgs[a].c.W * imgs[a].c.H > (int64_t)imgs[b].c.W * imgs[b].c.H;
   });
